@@ -1,0 +1,181 @@
+"""Pins of the oracle's forward map and gradient: the M-norm error bound of
+Sec. 3.3 against brute-force dense exp(-t M^-1 K) b, exact eigenvector
+behaviour, discrete charge conservation, two independent direct solvers,
+monotone decay, finite differences and the adjoint identity."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import tem_workloads as W
+from oracle import direct as D
+from oracle import mscg, rkfit, yee
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    # a milder air conductivity keeps the dense references accurate to ~1e-12
+    # (with 1e-8 S/m the eigenvalue range alone limits them to ~1e-8)
+    wl = W.small_case(5, seed=3, t=W.log_channels(1e-5, 1e-3, 10), sigma_air=1e-5)
+    P = yee.Problem(wl)
+    fit = rkfit.rkfit(wl.t, 24)
+    s, C = rkfit.shifts_and_coefficients(fit)
+    return wl, P, fit, s, C
+
+
+def test_dense_references_agree(tiny):
+    wl, P, *_ = tiny
+    a = D.dense_exact(P, wl.t[:4])
+    b = D.dense_expm(P, wl.t[:4])
+    assert np.all(D.m_norm(P, a - b) <= 1e-9 * D.m_norm(P, a))
+
+
+def test_m_norm_error_bound_vs_dense_expm(tiny):
+    """Sec. 3.3: ||exp(-t_k M^-1 K) b - r^[k](M^-1 K) b||_M <= ||b||_M err_k."""
+    wl, P, fit, s, C = tiny
+    X = D.solve_shifted(P, s, P.F[:, 0], "banded")
+    U = D.contract(X, C)
+    Ue = D.dense_exact(P, wl.t)
+    b = P.F[:, 0] / P.M
+    lhs = D.m_norm(P, U - Ue)
+    assert np.all(lhs <= 1.01 * fit["err"] * D.m_norm(P, b) + 1e-14 * D.m_norm(P, b))
+
+
+def test_eigenvector_gives_scalar_rational_function(tiny):
+    """For b an eigenvector of M^-1 K with eigenvalue lam, r^[k](M^-1 K) b =
+    r^[k](lam) b.  In a uniform, homogeneous PEC box the field
+    e_x = sin(q pi j/N) sin(r pi k/N) (any i), e_y = e_z = 0 is an exact
+    eigenvector with lam = 4/(mu0 sigma h^2) (sin^2(q pi/2N) + sin^2(r pi/2N))."""
+    wl, _, fit, s, C = tiny
+    N, h, sig = 5, 20.0, 0.01
+    g = yee.YeeGrid([h] * N, [h] * N, [h] * N)
+    m = g.interior()
+    K = g.stiffness_full()[m][:, m].tocsr()
+    M = g.mass_full(np.full((N, N, N), sig))[m]
+
+    class _P:  # the direct solver only needs K and M
+        pass
+    P = _P(); P.K, P.M = K, M
+    for q, r in [(1, 1), (2, 3), (4, 4)]:
+        e = np.zeros(g.n_edges)
+        kk, jj, ii = np.meshgrid(np.arange(N + 1), np.arange(N + 1), np.arange(N), indexing="ij")
+        e[:g.n_ex] = (np.sin(q * np.pi * jj / N) * np.sin(r * np.pi * kk / N)).ravel()
+        b = e[m]
+        lam = 4 / (yee.MU0 * sig * h * h) * (np.sin(q * np.pi / (2 * N)) ** 2 + np.sin(r * np.pi / (2 * N)) ** 2)
+        U = D.contract(D.solve_shifted(P, s, M * b), C)
+        rl = rkfit.evaluate(fit["xi"], fit["alpha"], np.array([lam]))[0]
+        floor = np.abs(C).T @ (1.0 / np.abs(lam + s))  # |terms| of the residue sum
+        err = np.abs(U - np.outer(b, rl)).max(axis=0) / np.abs(b).max()
+        assert np.all(err <= 1e-13 * np.abs(rl) + 1e-14 * floor)
+
+
+def test_direct_solvers_agree_and_residual(tiny):
+    wl, P, fit, s, C = tiny
+    Xb = D.solve_shifted(P, s, P.F[:, 0], "banded")
+    Xs = D.solve_shifted(P, s, P.F[:, 0], "splu")
+    assert np.all(D.m_norm(P, Xb - Xs) <= 1e-11 * D.m_norm(P, Xs))
+    f = P.F[:, 0]
+    for j, sj in enumerate(s):
+        r = f - (P.K @ Xb[:, j] + sj * P.M * Xb[:, j])
+        assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(f)
+
+
+def test_charge_conservation(tiny):
+    """G^T K = 0 and G^T f = 0 for a closed loop give G^T M x_j = 0 at every
+    interior node (the PEC walls carry surface charge, so boundary nodes are
+    excluded)."""
+    wl, P, fit, s, C = tiny
+    X = D.solve_shifted(P, s, P.F[:, 0])
+    g = P.grid
+    kk, jj, ii = np.meshgrid(np.arange(g.Nz + 1), np.arange(g.Ny + 1), np.arange(g.Nx + 1), indexing="ij")
+    inner = ((ii > 0) & (ii < g.Nx) & (jj > 0) & (jj < g.Ny) & (kk > 0) & (kk < g.Nz)).ravel()
+    G = g.gradient()[P.idx][:, np.where(inner)[0]]  # potentials vanishing on the PEC walls
+    aG, aK, f = abs(G), abs(P.K), P.F[:, 0]
+    for j, sj in enumerate(s):
+        x = X[:, j]
+        q = G.T @ (P.M * x)
+        # rounding floor of G^T (K x + s M x - f) / s, term by term
+        floor = (aG.T @ (aK @ np.abs(x) + abs(sj) * P.M * np.abs(x) + np.abs(f))) / abs(sj)
+        assert np.all(np.abs(q) <= 1e-10 * floor.max())
+
+
+def test_monotone_decay_plain16():
+    """||u(t_k)||_M is non-increasing in k up to the approximation error
+    (2 max_k err_k ||b||_M), and dB_z/dt at the loop centre is negative where
+    the channel is resolved (well above that error)."""
+    wl = W.cfg_plain16()
+    P = yee.Problem(wl)
+    fit = rkfit.rkfit(wl.t, wl.degree)
+    s, C = rkfit.shifts_and_coefficients(fit)
+    X = D.solve_shifted(P, s, P.F[:, 0], "banded")
+    U = D.contract(X, C)
+    un = D.m_norm(P, U)
+    bn = D.m_norm(P, P.F[:, 0] / P.M)
+    slack = 2 * fit["err"].max() * bn
+    assert np.all(np.diff(un) <= slack)
+    d = (P.Q @ U)[0]
+    resolved = un > 1e3 * fit["err"] * bn
+    assert resolved.sum() >= 8 and np.all(d[resolved] < 0)
+
+
+def test_multishift_cg_matches_direct(tiny):
+    wl, P, fit, s, C = tiny
+    Xd = D.solve_shifted(P, s, P.F[:, 0])
+    Xi, info = mscg.multishift_cg(P.K, P.M, P.F[:, 0], s, rtol=1e-13)
+    assert info["converged"]
+    assert np.all(D.m_norm(P, Xi - Xd) <= 1e-9 * D.m_norm(P, Xd))
+
+
+def _misfit_setup(seed=0):
+    wl = W.small_case(5, seed=seed, t=W.log_channels(1e-5, 1e-3, 8))
+    wl.receivers = [(1, 1), (2, 2), (3, 1)]
+    fit = rkfit.rkfit(wl.t, 20)
+    s, C = rkfit.shifts_and_coefficients(fit)
+    return wl, s, C
+
+
+def _prob_with(wl, sigma):
+    w2 = W.Workload(wl.name, wl.hx, wl.hy, wl.hz, wl.k_s, sigma, wl.loops, wl.receivers, wl.t)
+    return yee.Problem(w2)
+
+
+def test_adjoint_gradient_vs_central_differences():
+    """Sec. 4: the adjoint gradient of phi = 1/2 ||d(sigma) - d_obs||^2 w.r.t.
+    ln sigma_c agrees with central differences of the oracle's own data."""
+    wl, s, C = _misfit_setup()
+    rng = np.random.default_rng(1)
+    d_obs = D.data_for_model(lambda sg: _prob_with(wl, sg), wl.sigma, s, C) * (1 + 0.1 * rng.standard_normal((len(wl.t), 3)))
+    P = _prob_with(wl, wl.sigma)
+    d = D.data_for_model(lambda sg: P, wl.sigma, s, C)
+    grad = D.misfit_gradient(P, s, C, d - d_obs)
+    h = 1e-4
+    cells = [(0, 2, 2), (1, 1, 3), (2, 3, 2), (1, 2, 1)]
+    for (k, j, i) in cells:
+        c = (k * 5 + j) * 5 + i
+        vals = []
+        for sgn in (+1, -1):
+            sg = wl.sigma.copy()
+            sg[k, j, i] *= np.exp(sgn * h)
+            dd = D.data_for_model(lambda x: _prob_with(wl, x), sg, s, C)
+            vals.append(0.5 * np.sum((dd - d_obs) ** 2))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - grad[c]) <= 1e-5 * abs(grad[c]) + 1e-8 * np.abs(grad).max()
+
+
+def test_adjoint_bilinear_identity():
+    """<w, J dm> = <J^T w, dm> with J dm the directional derivative of the
+    data (computed by finite differences of the exact linearization)."""
+    wl, s, C = _misfit_setup(2)
+    P = _prob_with(wl, wl.sigma)
+    rng = np.random.default_rng(3)
+    w = rng.standard_normal((len(wl.t), 3))
+    g = D.misfit_gradient(P, s, C, w)       # J^T w
+    dm = np.zeros(g.shape)
+    dm[:50] = rng.standard_normal(50)       # earth cells only (bottom layers)
+    # J dm by the forward sensitivity: dx_j = -A_j^-1 (s_j dM x_j)
+    X = D.solve_shifted(P, s, P.F[:, 0])
+    dM = P.mass_derivative() @ dm
+    dX = np.zeros_like(X)
+    for j, sj in enumerate(s):
+        dX[:, j] = -D.solve_shifted(P, [sj], sj * dM * X[:, j])[:, 0]
+    Jdm = (P.Q @ D.contract(dX, C)).T
+    assert np.isclose(np.sum(w * Jdm), g @ dm, rtol=1e-10)
