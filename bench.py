@@ -1,0 +1,145 @@
+"""Benchmark: forward TEM models on the 64^3 graded grid (plain FP64 path).
+
+One step = one forward model through the library: set the conductivity
+(lumped mass and scaling on the device), solve all J shifted systems with
+the shared multi-shift recurrence, form all 40 channels of the full field by
+the MFMA residue contraction, and read dB_z/dt at the receiver.  The poles
+and residues (host RKFIT) are computed once per channel set, before the
+timed region.
+
+Prints one JSON line (see the README of this repository for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "shifted-system unknown-updates/s + forward TEM models/s; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(kind, ctx_dims, J_apply, B):
+    """Bytes a launch must move at minimum (each array once):
+       stencil: read r, p_old, M^-1/2, write p_new, q on the 3 nx ny nz owned edges (40 B each);
+       update:  read r, q, write r_next on all 3 (nx+1)(ny+1)(nz+1) padded entries (24 B);
+       block:   read the B residuals (8 B each) and read+write x_j, p_j (64 B per shift)."""
+    nx, ny, nz = ctx_dims
+    owned = 3 * nx * ny * nz
+    padded = 3 * (nx + 1) * (ny + 1) * (nz + 1)
+    if kind == 0:
+        return 40.0 * owned
+    if kind == 1:
+        return 24.0 * padded
+    return (8.0 * B + 64.0 * J_apply) * padded
+
+
+def cpu_baseline(wl, s, seconds):
+    """The oracle's plain CSR multi-shift CG on the same problem, bounded in time."""
+    from oracle import mscg, yee
+    import threadpoolctl  # noqa: F401  (numpy/scipy thread count is reported below)
+    P = yee.Problem(wl)
+    t0 = time.time()
+    _, info = mscg.multishift_cg(P.K, P.M, P.F[:, 0], s, rtol=1e-12, max_seconds=seconds)
+    dt = time.time() - t0
+    upd = float(P.n) * float(info["per_shift"].sum())
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:
+        cores = 1
+    return {"value": upd / dt, "unit": "unknown-updates/s", "cores": int(cores), "kind": "oracle",
+            "sample": "oracle multi-shift CG (CSR, numpy/scipy) on the same 64^3 problem and poles, "
+                      "%d seed iterations in %.1f s (a direct factorization of one 64^3 shifted "
+                      "system does not fit in memory)" % (info["iterations"], dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="graded64", choices=["graded64", "plain16", "blocky128"])
+    ap.add_argument("--block", type=int, default=32)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fields", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(sharding over poles or requests is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import tem_workloads as W
+    from paper_2506_11657_amd import tem
+
+    wl = {"graded64": W.cfg_graded64, "plain16": W.cfg_plain16, "blocky128": W.cfg_blocky128}[args.config]()
+    xi, c, err = tem.poles(wl.t, wl.degree)
+    J, T = c.shape
+    torch.cuda.set_device(0)
+    ctx = tem.Context(wl.hx, wl.hy, wl.hz, wl.k_s, device=0)
+    fields = None if args.no_fields else torch.zeros((1, T, ctx.n_storage), dtype=torch.float64, device="cuda")
+
+    def step(profile=False):
+        ctx.set_conductivity(wl.sigma)
+        return ctx.forward(wl.loops, wl.receivers, xi, c, fields=fields, block=args.block, profile=profile)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    lat, upd, last = [], 0.0, None
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        a = time.perf_counter()
+        data, st = step(profile=True)
+        lat.append(time.perf_counter() - a)
+        upd += st["unknown_updates"]
+        last = st
+        print("step %d: %.1f ms, %d iterations" % (i, 1e3 * lat[-1], st["iterations"]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    # roofline of the dominant kernel class (HIP-event time on the library's stream)
+    ms, n = last["kernel_ms"], last["kernel_launches"]
+    kind = int(np.argmax(ms[:3]))
+    avg_s = ms[kind] / max(n[kind], 1) / 1e3
+    J_apply = J
+    nbytes = algorithmic_bytes(kind, (len(wl.hx), len(wl.hy), len(wl.hz)), J_apply, args.block)
+    achieved = nbytes / avg_s / 1e9
+    names = ["seed_stencil", "seed_update", "block_update"]
+    out = {
+        "metric": METRIC,
+        "value": upd / dt,
+        "unit": "unknown-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic (seeded)",
+        "config": {"workload": wl.name, "grid": list(wl.shape), "n_unknowns": ctx.n_unknowns,
+                   "shifts_J": J, "channels_T": T, "degree": wl.degree, "receivers": len(wl.receivers),
+                   "block": args.block, "fields": fields is not None},
+        "models_per_s": args.steps / dt,
+        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
+        "iterations": last["iterations"],
+        "true_res_max": max(last["true_res"]),
+        "kernel_ms_per_step": {names[i]: ms[i] for i in range(3)},
+        "roofline": {"bound": "hbm", "kernel": names[kind], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": 1e6 * avg_s, "algorithmic_bytes_per_launch": nbytes},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, -xi, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

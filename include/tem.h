@@ -1,0 +1,181 @@
+/*
+ * tem.h -- C ABI of the MI355X (gfx950) library for transient electromagnetic
+ * forward modelling with a shared-pole rational approximant of exp(-t M^-1 K).
+ *
+ * The method (Borner & Guttel, "Fast parallel transient electromagnetic
+ * modeling using a uniform-in-time approximation to the exponential"):
+ *   eq. (ode):   K u + M u' = 0,  M u(0) = f   (curl-curl stiffness K, conductivity
+ *                mass M, loop source f; Sec. 2.2)
+ *   eq. (expm):  u(t) = exp(-t M^-1 K) b,  b = M^-1 f
+ *   eq. (ratfam) and (rmj):  one set of poles xi_i for all channels t_k,
+ *                u(t_k) ~ Re sum_j c_j(t_k) x_j,   (K - xi_j M) x_j = f,
+ *   with c_j(t_k) = 2 alpha_j^[k] for a conjugate pair and alpha_j^[k] for a
+ *   real pole, and all channels formed at once as the product S R (Sec. 3.2).
+ *
+ * Discretization: a tensor grid of nx*ny*nz hexahedral cells with one unknown
+ * per edge (tangential E at the edge midpoint, lumped mass), PEC walls.
+ *
+ * Conventions shared by every entry point:
+ *   - cells (i, j, k) with x fastest; k = 0 is the bottom layer, z points up;
+ *     per-cell arrays are [nz][ny][nx];
+ *   - "storage edge order": Ex[nz+1][ny+1][nx], then Ey[nz+1][ny][nx+1], then
+ *     Ez[nz][ny+1][nx+1], x fastest; n_storage = sum of the three; boundary
+ *     edges are present and zero;
+ *   - all floating point is IEEE binary64 unless stated;
+ *   - complex arrays are interleaved (re, im) pairs of doubles;
+ *   - pointers are host pointers unless the argument says "device";
+ *   - the caller owns every buffer it passes; the context owns its device
+ *     workspace and frees it in tem_destroy;
+ *   - every call is ordered on the context's HIP stream; calls that return
+ *     host data synchronize that stream before returning;
+ *   - one context must not be used by two threads at once.
+ *
+ * Errors: every int-returning call returns TEM_OK (0) or a negative status
+ * below; tem_last_error gives a message.  On error the outputs are
+ * unspecified, except that TEM_ENOCONV still fills the stats and the outputs
+ * from the best iterate.
+ */
+#ifndef TEM_H
+#define TEM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TEM_MAX_SHIFTS 64
+
+enum tem_status {
+  TEM_OK = 0,
+  TEM_EINVAL = -1,      /* invalid argument (sizes, non-finite or non-positive values, geometry) */
+  TEM_ENOMEM = -2,      /* device allocation failed or request exceeds the device budget */
+  TEM_ENOCONV = -3,     /* a shifted system did not reach rtol within max_iter */
+  TEM_EBREAKDOWN = -4,  /* Krylov breakdown (zero or non-finite recurrence coefficient) */
+  TEM_EHIP = -5,        /* a HIP runtime call failed */
+  TEM_ESTATE = -6       /* call out of order (e.g. adjoint without a matching forward) */
+};
+
+/* flags for tem_set_conductivity */
+#define TEM_SIGMA_LOG 1     /* input is ln(sigma) instead of sigma */
+#define TEM_DEVICE_PTR 2    /* input/output pointer is a device pointer */
+
+typedef struct tem_ctx tem_ctx;
+
+/* Rectangular transmitter loop on node lines of the surface node plane k_s:
+ * corners at nodes (i0, j0) and (i1, j1), 0 < i0 < i1 < nx, 0 < j0 < j1 < ny,
+ * current `current` [A] counter-clockwise seen from +z.  Its source vector is
+ * f_e = current * l_e * (+-1) on the loop edges (Sec. 2.1 step-off source,
+ * f = (q, Phi) of Sec. 2.2). */
+typedef struct { int i0, i1, j0, j1; double current; } tem_loop;
+
+/* Receiver on the surface z-face of cell column (i, j) in node plane k_s,
+ * 0 <= i < nx, 0 <= j < ny.  It records dB_z/dt = -(curl e)_z =
+ * -(circulation of e around the face)/(face area) (Sec. 5 observation). */
+typedef struct { int i, j; } tem_receiver;
+
+typedef struct {
+  int precision;     /* 0: FP64 Krylov sweeps; 1: FP32 sweeps + FP64 residual refinement */
+  double rtol;       /* per-shift stop: |zeta_j| ||r||_2 <= rtol ||g||_2 in the scaled system;
+                        <= 0 selects 1e-12 (FP64) */
+  int max_iter;      /* cap on seed iterations per solve; <= 0 selects 200000 */
+  int block;         /* iterations between deferred shift updates (1..64); <= 0 selects 32 */
+  double seed_shift; /* real seed shift of the shared recurrence; <= 0 selects
+                        max(min_j Re s_j, 1e-3 min_j |s_j|), s_j = -xi_j */
+  int refine_max;    /* precision 1: cap on refinement passes; <= 0 selects 8 */
+  int keep_solutions;/* nonzero: keep X on the device for tem_adjoint / tem_solutions */
+  int profile;       /* nonzero: time every solver kernel launch with HIP events on the
+                        context stream (fills kernel_ms / kernel_launches of tem_stats) */
+} tem_solve_opts;
+
+/* kernel classes reported by tem_stats.kernel_ms */
+#define TEM_K_STENCIL 0     /* seed stencil: p = r + beta p; q = (A + s0) p; (p, q) */
+#define TEM_K_UPDATE 1      /* seed update: r -= alpha q; (r, r); shifted recurrences */
+#define TEM_K_BLOCK 2       /* deferred shift update of x_j, p_j every block */
+#define TEM_K_OTHER 3       /* init, true residual, contraction, receivers */
+
+typedef struct {
+  int iterations;                       /* seed iterations of the last source */
+  int converged;                        /* 1 if every shift met rtol */
+  int n_shifts;
+  int iters_per_shift[TEM_MAX_SHIFTS];  /* iterations while shift j was active (last source) */
+  double est_res[TEM_MAX_SHIFTS];       /* |zeta_j| ||r|| / ||g|| at the stop (last source) */
+  double true_res[TEM_MAX_SHIFTS];      /* FP64 ||g - (A + s_j) y_j|| / ||g|| (last source) */
+  int refine_passes;                    /* precision 1 */
+  double seconds;                       /* wall time of the call */
+  double unknown_updates;               /* sum over sources and shifts of n * active iterations */
+  double kernel_ms[4];                  /* with opts->profile: summed HIP-event time per kernel class */
+  long long kernel_launches[4];         /* with opts->profile: launches per kernel class */
+} tem_stats;
+
+/* Create a context for an nx*ny*nz grid with cell widths hx[nx], hy[ny], hz[nz]
+ * [m] (all > 0 and finite) and the ground surface at node plane k_surface
+ * (0 < k_surface < nz).  device: HIP device ordinal.  hip_stream: a hipStream_t
+ * cast to void*, or NULL for the default stream.  On success *ctx owns device
+ * memory for the operator coefficients; no conductivity is set yet. */
+int tem_setup_grid(tem_ctx **ctx, int nx, int ny, int nz,
+                   const double *hx, const double *hy, const double *hz,
+                   int k_surface, int device, void *hip_stream);
+
+/* Set the per-cell conductivity sigma[nz][ny][nx] [S/m] (or ln sigma with
+ * TEM_SIGMA_LOG), which defines the lumped mass M (Sec. 2.2, [M]_ij =
+ * (sigma Phi_j, Phi_i)).  Values must be finite and sigma > 0.  With
+ * TEM_DEVICE_PTR the array is read from device memory.  Invalidates any
+ * stored forward state. */
+int tem_set_conductivity(tem_ctx *ctx, const double *sigma, int flags);
+
+/* Shared poles and residues for the channels t[T] (t > 0, finite) by RKFIT
+ * (Sec. 3.2, eq. (ratfam), objective eq. (rkfit) with weights w[T], NULL ->
+ * all 1).  degree: the number of poles m-hat (2..2*TEM_MAX_SHIFTS); 0 picks
+ * the Table 1 degree for tol and the ratio max(t)/min(t).  Outputs, for the
+ * J <= J_max poles kept (one per conjugate pair, with Im > 0, then the real
+ * poles):
+ *   xi[2*J]    the poles xi_j (re, im) [1/s];
+ *   c[2*J*T]   c_j(t_k) at c[2*(j*T + k)] (re, im) with the factor 2 of a
+ *              pair folded in, so u(t_k) = Re sum_j c_j(t_k) x_j;
+ *   err[T]     eq. (error): max_{x>=0} |exp(-t_k x) - r^[k](x)| (may be NULL).
+ * Host only; uses no device. */
+int tem_poles(int T, const double *t, const double *w, int degree, double tol,
+              int J_max, int *J, double *xi, double *c, double *err);
+
+/* Forward model (Sec. 3.2): for each of the n_src loops, solve the J shifted
+ * complex-symmetric systems (K - xi_j M) x_j = f on the device and form
+ *   data[(s*T + k)*n_rx + r] = dB_z/dt at receiver r, channel k   [T/s]  (host)
+ *   fields (optional, device, NULL to skip): u(t_k) in storage edge order at
+ *          fields[(s*T + k)*n_storage + e]                          [V/m]
+ * xi[2*J] and c[2*J*T] are as produced by tem_poles (host).  opts may be NULL
+ * (defaults), stats may be NULL.  With opts->keep_solutions the solutions of
+ * every source stay on the device for tem_adjoint and tem_solutions. */
+int tem_forward(tem_ctx *ctx, const tem_loop *src, int n_src,
+                const tem_receiver *rx, int n_rx, int T, int J,
+                const double *xi, const double *c, const tem_solve_opts *opts,
+                double *data, double *fields, tem_stats *stats);
+
+/* Adjoint (Sec. 4): given w[(s*T + k)*n_rx + r] = dphi/d data (host) for the
+ * last tem_forward call (which must have set keep_solutions), compute
+ *   grad[c] = dphi/d ln sigma_c = -Re sum_s sum_j s_j lambda_j^T (dM/d ln sigma_c) x_j,
+ *   (K + s_j M) lambda_j = sum_k c_j(t_k) Q^T w_k,  s_j = -xi_j,
+ * for every cell c (grad[nz*ny*nx], host).  Returns TEM_ESTATE if there is
+ * no matching forward state. */
+int tem_adjoint(tem_ctx *ctx, const double *w, double *grad_log_sigma, tem_stats *stats);
+
+/* Copy the stored solutions x_j of source s (storage edge order, complex):
+ * X[2*(j*n_storage + e)] (re, im), host.  Needs keep_solutions. */
+int tem_solutions(tem_ctx *ctx, int s, double *X);
+
+/* Apply the shifted operator: y = (K + shift M) x for a complex vector x in
+ * storage edge order (host, interleaved); boundary entries of x are ignored
+ * and those of y are zero.  For operator checks. */
+int tem_apply(tem_ctx *ctx, double shift_re, double shift_im, const double *x, double *y);
+
+/* Sizes: n_storage edges and n interior unknowns of the context's grid. */
+int tem_sizes(const tem_ctx *ctx, long long *n_storage, long long *n_unknowns);
+
+void tem_destroy(tem_ctx *ctx);
+
+/* Message of the last failing call on ctx (or of the last failing
+ * context-less call when ctx is NULL).  Valid until the next call. */
+const char *tem_last_error(const tem_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TEM_H */

@@ -1,0 +1,612 @@
+// C ABI of the TEM library (include/tem.h): context, validation and the
+// orchestration of the device kernels in tem_kernels.hip.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/tem.h"
+#include "tem_internal.h"
+
+using tem::GridArgs;
+using tem::SolveState;
+
+namespace {
+
+thread_local std::string g_global_error;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct tem_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int nx = 0, ny = 0, nz = 0, ks = 0;
+  std::vector<double> hx, hy, hz;
+  GridArgs g{};
+  long long n3 = 0, nstore = 0, nunk = 0;
+  // operator data
+  double* d_axis = nullptr;  // 9 arrays of length max(n)+1
+  double* d_sigma = nullptr;
+  double* d_mass = nullptr;
+  double* d_dinv = nullptr;
+  double* d_sqrtm = nullptr;
+  bool has_sigma = false;
+  // solver workspace
+  SolveState* d_state = nullptr;
+  double* d_partials = nullptr;
+  unsigned int* d_counters = nullptr;
+  DevBuf R, pbuf, q, gvec, gc, f, P, C, rx, data, res, cpart, sh;
+  std::vector<DevBuf> Y;  // per source (kept) or one
+  // stored forward state for the adjoint
+  bool fwd_valid = false;
+  int fwd_J = 0, fwd_T = 0, fwd_nsrc = 0, fwd_nrx = 0;
+  std::vector<double> fwd_xi, fwd_c;
+  std::vector<tem_receiver> fwd_rx;
+  std::vector<tem_loop> fwd_src;
+  tem_solve_opts fwd_opts{};
+  std::string err;
+  // kernel timing (opts.profile)
+  double prof_ms[4] = {0, 0, 0, 0};
+  long long prof_n[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+int fail(tem_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  else g_global_error = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                      \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail(ctx, TEM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+int ensure(tem_ctx* ctx, DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes) return TEM_OK;
+  if (b.p) {
+    hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  if (hipMalloc(&b.p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, TEM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  if (hipMemsetAsync(b.p, 0, bytes, ctx->stream) != hipSuccess)
+    return fail(ctx, TEM_EHIP, "hipMemsetAsync failed");
+  b.bytes = bytes;
+  return TEM_OK;
+}
+
+void release(DevBuf& b) {
+  if (b.p) hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+bool finite_pos(const double* a, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!(std::isfinite(a[i]) && a[i] > 0.0)) return false;
+  return true;
+}
+
+long long node_index(const tem_ctx* c, int i, int j, int k) {
+  return ((long long)k * (c->ny + 1) + j) * (c->nx + 1) + i;
+}
+
+// Source vector f_e = I l_e (+-1) on the loop edges, node-padded layout.
+void loop_source(const tem_ctx* c, const tem_loop& L, std::vector<double>& f) {
+  const long long nn = c->g.nn;
+  std::fill(f.begin(), f.end(), 0.0);
+  for (int i = L.i0; i < L.i1; ++i) {
+    f[0 * nn + node_index(c, i, L.j0, c->ks)] += L.current * c->hx[i];
+    f[0 * nn + node_index(c, i, L.j1, c->ks)] -= L.current * c->hx[i];
+  }
+  for (int j = L.j0; j < L.j1; ++j) {
+    f[1 * nn + node_index(c, L.i1, j, c->ks)] += L.current * c->hy[j];
+    f[1 * nn + node_index(c, L.i0, j, c->ks)] -= L.current * c->hy[j];
+  }
+}
+
+int check_loops(tem_ctx* ctx, const tem_loop* src, int n_src) {
+  if (n_src < 1 || src == nullptr) return fail(ctx, TEM_EINVAL, "need at least one loop source");
+  for (int s = 0; s < n_src; ++s) {
+    const tem_loop& L = src[s];
+    if (!(0 < L.i0 && L.i0 < L.i1 && L.i1 < ctx->nx && 0 < L.j0 && L.j0 < L.j1 && L.j1 < ctx->ny))
+      return fail(ctx, TEM_EINVAL, "loop " + std::to_string(s) + " is not on interior node lines");
+    if (!std::isfinite(L.current) || L.current == 0.0)
+      return fail(ctx, TEM_EINVAL, "loop current must be finite and nonzero");
+  }
+  return TEM_OK;
+}
+
+tem_solve_opts resolve_opts(const tem_solve_opts* o) {
+  tem_solve_opts r{};
+  if (o) r = *o;
+  if (!(r.rtol > 0.0)) r.rtol = 1e-12;
+  if (r.max_iter <= 0) r.max_iter = 200000;
+  if (r.block <= 0) r.block = 32;
+  if (r.refine_max <= 0) r.refine_max = 8;
+  return r;
+}
+
+int block_length(int requested, int J) {
+  // compiled block lengths; the coefficient table must fit in 64 KiB of LDS
+  int B = requested >= 64 ? 64 : requested >= 32 ? 32 : requested >= 16 ? 16 : 8;
+  while (B > 8 && (long long)J * (2 * B + 2) * 16 > 65536) B /= 2;
+  return B;
+}
+
+// One multi-shift solve (all J shifts, one right-hand side) on the device.
+// Y receives the scaled solutions y_j = M^{1/2} x_j (node-padded, complex).
+int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const std::vector<double>& shifts_im,
+                     double s0, const tem_solve_opts& o, double2* Y, SolveState& host_state, double& seconds) {
+  const int J = (int)shifts_re.size();
+  const int B = block_length(o.block, J);
+  hipStream_t st = ctx->stream;
+  const GridArgs& g = ctx->g;
+  int rc;
+  if ((rc = ensure(ctx, ctx->R, (size_t)B * ctx->n3 * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->pbuf, 2 * ctx->n3 * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->q, ctx->n3 * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->P, (size_t)J * ctx->n3 * sizeof(double2)))) return rc;
+  double* R = (double*)ctx->R.p;
+  double* pb = (double*)ctx->pbuf.p;
+  double* q = (double*)ctx->q.p;
+  double2* P = (double2*)ctx->P.p;
+
+  std::unique_ptr<SolveState> hs(new SolveState());
+  std::memset(hs.get(), 0, sizeof(SolveState));
+  hs->J = J;
+  hs->B = B;
+  hs->tol2 = o.rtol * o.rtol;
+  for (int j = 0; j < J; ++j) {
+    hs->sig_re[j] = shifts_re[j] - s0;
+    hs->sig_im[j] = shifts_im[j];
+    hs->z_re[j] = hs->zp_re[j] = 1.0;
+    hs->active[j] = 1;
+    hs->apply[j] = 1;
+    hs->a_re[j] = 1.0;
+  }
+  HIPCHK(ctx, hipMemcpyAsync(ctx->d_state, hs.get(), sizeof(SolveState), hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemsetAsync(ctx->d_counters, 0, 16 * sizeof(unsigned int), st));
+  tem::Reduce red{ctx->d_partials, ctx->d_counters};
+  auto t0 = std::chrono::steady_clock::now();
+  tem::launch_seed_init(g, (const double*)ctx->gvec.p, R, pb + ctx->n3, Y, P, J, red, ctx->d_state, st);
+  HIPCHK(ctx, hipGetLastError());
+
+  struct Head {
+    double rr, rr0, pAp, alpha, beta, alpha_prev, beta_prev, tol2;
+    int k, n_active, breakdown;
+  } head{};
+  // optional per-launch timing: one event pair per launch of the block
+  std::vector<hipEvent_t> ev;
+  if (o.profile) {
+    ev.resize(2 * (2 * B + 1));
+    for (auto& e : ev) HIPCHK(ctx, hipEventCreate(&e));
+  }
+  auto mark = [&](int slot) {
+    if (o.profile) (void)hipEventRecord(ev[slot], st);
+  };
+  int k = 0;
+  bool done = false;
+  int rc_loop = TEM_OK;
+  while (!done && k < o.max_iter) {
+    for (int i = 0; i < B; ++i, ++k) {
+      double* r = R + (size_t)(k % B) * ctx->n3;
+      double* rn = R + (size_t)((k + 1) % B) * ctx->n3;
+      double* pold = pb + (size_t)((k + 1) & 1) * ctx->n3;
+      double* pnew = pb + (size_t)(k & 1) * ctx->n3;
+      mark(4 * i);
+      tem::launch_seed_stencil(g, r, pold, pnew, q, ctx->d_dinv, s0, red, ctx->d_state, st);
+      mark(4 * i + 1);
+      mark(4 * i + 2);
+      tem::launch_seed_update(g, r, q, rn, red, ctx->d_state, (k + 1) % B, st);
+      mark(4 * i + 3);
+    }
+    mark(4 * B);
+    tem::launch_block_update(g, R, Y, P, J, B, ctx->d_state, st);
+    mark(4 * B + 1);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipMemcpyAsync(&head, ctx->d_state, sizeof(Head), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    if (o.profile) {
+      for (int i = 0; i < B; ++i) {
+        float a = 0.f, b = 0.f;
+        (void)hipEventElapsedTime(&a, ev[4 * i], ev[4 * i + 1]);
+        (void)hipEventElapsedTime(&b, ev[4 * i + 2], ev[4 * i + 3]);
+        ctx->prof_ms[TEM_K_STENCIL] += a;
+        ctx->prof_ms[TEM_K_UPDATE] += b;
+      }
+      float c = 0.f;
+      (void)hipEventElapsedTime(&c, ev[4 * B], ev[4 * B + 1]);
+      ctx->prof_ms[TEM_K_BLOCK] += c;
+      ctx->prof_n[TEM_K_STENCIL] += B;
+      ctx->prof_n[TEM_K_UPDATE] += B;
+      ctx->prof_n[TEM_K_BLOCK] += 1;
+    }
+    if (head.breakdown) break;
+    if (head.n_active == 0) done = true;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  (void)rc_loop;
+  seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  HIPCHK(ctx, hipMemcpyAsync(&host_state, ctx->d_state, sizeof(SolveState), hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  if (host_state.breakdown) return fail(ctx, TEM_EBREAKDOWN, "Krylov breakdown in the shared recurrence");
+  if (host_state.n_active > 0) return fail(ctx, TEM_ENOCONV, "max_iter reached before every shift converged");
+  return TEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tem_setup_grid(tem_ctx** out, int nx, int ny, int nz, const double* hx, const double* hy, const double* hz,
+                   int k_surface, int device, void* hip_stream) {
+  if (out == nullptr) return fail(nullptr, TEM_EINVAL, "ctx pointer is NULL");
+  *out = nullptr;
+  if (nx < 2 || ny < 2 || nz < 2 || nx > 4096 || ny > 4096 || nz > 4096)
+    return fail(nullptr, TEM_EINVAL, "grid dimensions must be in [2, 4096]");
+  if (!hx || !hy || !hz || !finite_pos(hx, nx) || !finite_pos(hy, ny) || !finite_pos(hz, nz))
+    return fail(nullptr, TEM_EINVAL, "cell widths must be finite and positive");
+  if (!(0 < k_surface && k_surface < nz)) return fail(nullptr, TEM_EINVAL, "k_surface must satisfy 0 < k_surface < nz");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(nullptr, TEM_EHIP, "no such HIP device");
+  if (hipSetDevice(device) != hipSuccess) return fail(nullptr, TEM_EHIP, "hipSetDevice failed");
+  std::unique_ptr<tem_ctx> c(new tem_ctx());
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->nx = nx;
+  c->ny = ny;
+  c->nz = nz;
+  c->ks = k_surface;
+  c->hx.assign(hx, hx + nx);
+  c->hy.assign(hy, hy + ny);
+  c->hz.assign(hz, hz + nz);
+  GridArgs& g = c->g;
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.px = nx + 1;
+  g.py = ny + 1;
+  g.pz = nz + 1;
+  g.nn = (long long)g.px * g.py * g.pz;
+  c->n3 = 3 * g.nn;
+  c->nstore = tem::storage_edges(g);
+  c->nunk = (long long)nx * (ny - 1) * (nz - 1) + (long long)(nx - 1) * ny * (nz - 1) + (long long)(nx - 1) * (ny - 1) * nz;
+  // axis arrays: h, 1/h, dual/mu0 per axis, each padded to n+1
+  const int L = std::max(nx, std::max(ny, nz)) + 1;
+  std::vector<double> ax(9 * (size_t)L, 0.0);
+  const std::vector<double>* hs[3] = {&c->hx, &c->hy, &c->hz};
+  for (int a = 0; a < 3; ++a) {
+    const std::vector<double>& h = *hs[a];
+    const int n = (int)h.size();
+    double* H = &ax[(3 * a + 0) * (size_t)L];
+    double* IH = &ax[(3 * a + 1) * (size_t)L];
+    double* DW = &ax[(3 * a + 2) * (size_t)L];
+    for (int i = 0; i < n; ++i) {
+      H[i] = h[i];
+      IH[i] = 1.0 / h[i];
+    }
+    for (int i = 0; i <= n; ++i) {
+      const double lo = i > 0 ? h[i - 1] : 0.0, hi = i < n ? h[i] : 0.0;
+      DW[i] = 0.5 * (lo + hi) / tem::kMu0;  // node-centred dual width over mu0
+    }
+  }
+  tem_ctx* ctx = c.get();
+  HIPCHK(ctx, hipMalloc(&c->d_axis, ax.size() * sizeof(double)));
+  HIPCHK(ctx, hipMemcpy(c->d_axis, ax.data(), ax.size() * sizeof(double), hipMemcpyHostToDevice));
+  for (int a = 0; a < 3; ++a) {
+    g.h[a] = c->d_axis + (3 * a + 0) * (size_t)L;
+    g.ih[a] = c->d_axis + (3 * a + 1) * (size_t)L;
+    g.dw[a] = c->d_axis + (3 * a + 2) * (size_t)L;
+  }
+  const long long ncell = (long long)nx * ny * nz;
+  HIPCHK(ctx, hipMalloc(&c->d_sigma, ncell * sizeof(double)));
+  HIPCHK(ctx, hipMalloc(&c->d_mass, c->n3 * sizeof(double)));
+  HIPCHK(ctx, hipMalloc(&c->d_dinv, c->n3 * sizeof(double)));
+  HIPCHK(ctx, hipMalloc(&c->d_sqrtm, c->n3 * sizeof(double)));
+  HIPCHK(ctx, hipMalloc(&c->d_state, sizeof(SolveState)));
+  HIPCHK(ctx, hipMalloc(&c->d_partials, 2 * tem::kReduceSlots * sizeof(double)));
+  HIPCHK(ctx, hipMalloc(&c->d_counters, 16 * sizeof(unsigned int)));
+  HIPCHK(ctx, hipMemset(c->d_counters, 0, 16 * sizeof(unsigned int)));
+  *out = c.release();
+  return TEM_OK;
+}
+
+int tem_set_conductivity(tem_ctx* ctx, const double* sigma, int flags) {
+  if (!ctx) return fail(nullptr, TEM_EINVAL, "ctx is NULL");
+  if (!sigma) return fail(ctx, TEM_EINVAL, "sigma is NULL");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  const long long ncell = (long long)ctx->nx * ctx->ny * ctx->nz;
+  std::vector<double> h(ncell);
+  if (flags & TEM_DEVICE_PTR) {
+    HIPCHK(ctx, hipMemcpy(h.data(), sigma, ncell * sizeof(double), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(h.data(), sigma, ncell * sizeof(double));
+  }
+  for (long long i = 0; i < ncell; ++i) {
+    if (flags & TEM_SIGMA_LOG) {
+      if (!std::isfinite(h[i])) return fail(ctx, TEM_EINVAL, "ln sigma must be finite");
+      h[i] = std::exp(h[i]);
+    }
+    if (!(std::isfinite(h[i]) && h[i] > 0.0)) return fail(ctx, TEM_EINVAL, "sigma must be finite and positive");
+  }
+  HIPCHK(ctx, hipMemcpyAsync(ctx->d_sigma, h.data(), ncell * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  tem::launch_mass(ctx->g, ctx->d_sigma, ctx->d_mass, ctx->d_dinv, ctx->d_sqrtm, ctx->stream);
+  HIPCHK(ctx, hipGetLastError());
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->has_sigma = true;
+  ctx->fwd_valid = false;
+  return TEM_OK;
+}
+
+int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver* rx, int n_rx, int T, int J,
+                const double* xi, const double* c, const tem_solve_opts* opts, double* data, double* fields,
+                tem_stats* stats) {
+  auto t_start = std::chrono::steady_clock::now();
+  if (!ctx) return fail(nullptr, TEM_EINVAL, "ctx is NULL");
+  if (!ctx->has_sigma) return fail(ctx, TEM_ESTATE, "conductivity not set");
+  int rc;
+  if ((rc = check_loops(ctx, src, n_src))) return rc;
+  if (n_rx < 0 || (n_rx > 0 && (!rx || !data))) return fail(ctx, TEM_EINVAL, "bad receiver arguments");
+  for (int r = 0; r < n_rx; ++r)
+    if (rx[r].i < 0 || rx[r].i >= ctx->nx || rx[r].j < 0 || rx[r].j >= ctx->ny)
+      return fail(ctx, TEM_EINVAL, "receiver " + std::to_string(r) + " outside the surface");
+  if (T < 1 || T > 64) return fail(ctx, TEM_EINVAL, "T must be in [1, 64]");
+  if (J < 1 || J > TEM_MAX_SHIFTS || !xi || !c) return fail(ctx, TEM_EINVAL, "J must be in [1, 64] with xi and c");
+  std::vector<double> sre(J), sim(J);
+  for (int j = 0; j < J; ++j) {
+    if (!std::isfinite(xi[2 * j]) || !std::isfinite(xi[2 * j + 1])) return fail(ctx, TEM_EINVAL, "non-finite pole");
+    sre[j] = -xi[2 * j];  // shifts s_j = -xi_j of (K + s_j M) x_j = f
+    sim[j] = -xi[2 * j + 1];
+    if (sre[j] <= 0.0 && sim[j] == 0.0) return fail(ctx, TEM_EINVAL, "a real pole on x >= 0 makes K - xi M singular");
+  }
+  for (long long i = 0; i < 2LL * J * T; ++i)
+    if (!std::isfinite(c[i])) return fail(ctx, TEM_EINVAL, "non-finite residue");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  const tem_solve_opts o = resolve_opts(opts);
+  if (o.precision != 0) return fail(ctx, TEM_EINVAL, "precision 1 is not available in this build");
+  double s0 = o.seed_shift;
+  if (!(s0 > 0.0)) {
+    double minre = 1e300, minabs = 1e300;
+    for (int j = 0; j < J; ++j) {
+      minre = std::min(minre, sre[j]);
+      minabs = std::min(minabs, std::hypot(sre[j], sim[j]));
+    }
+    s0 = std::max(minre, 1e-3 * minabs);
+  }
+  hipStream_t st = ctx->stream;
+  const size_t ysz = (size_t)J * ctx->n3 * sizeof(double2);
+  const int nY = o.keep_solutions ? n_src : 1;
+  if ((int)ctx->Y.size() < nY) ctx->Y.resize(nY);
+  for (int s = 0; s < nY; ++s)
+    if ((rc = ensure(ctx, ctx->Y[s], ysz))) return rc;
+  if ((rc = ensure(ctx, ctx->gvec, ctx->n3 * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->gc, ctx->n3 * sizeof(double2)))) return rc;
+  if ((rc = ensure(ctx, ctx->f, ctx->n3 * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->C, 2 * (size_t)J * T * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->rx, 2 * (size_t)std::max(n_rx, 1) * sizeof(int)))) return rc;
+  if ((rc = ensure(ctx, ctx->data, (size_t)T * std::max(n_rx, 1) * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->sh, 4 * (size_t)TEM_MAX_SHIFTS * sizeof(double)))) return rc;
+  const int cpb = tem::cstencil_partials(ctx->g);
+  if ((rc = ensure(ctx, ctx->cpart, (size_t)J * cpb * sizeof(double)))) return rc;
+  HIPCHK(ctx, hipMemcpyAsync(ctx->C.p, c, 2 * (size_t)J * T * sizeof(double), hipMemcpyHostToDevice, st));
+  std::vector<int> rxi(2 * std::max(n_rx, 1), 0);
+  for (int r = 0; r < n_rx; ++r) {
+    rxi[2 * r] = rx[r].i;
+    rxi[2 * r + 1] = rx[r].j;
+  }
+  HIPCHK(ctx, hipMemcpyAsync(ctx->rx.p, rxi.data(), rxi.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  double* shd = (double*)ctx->sh.p;
+  HIPCHK(ctx, hipMemcpyAsync(shd, sre.data(), J * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(shd + TEM_MAX_SHIFTS, sim.data(), J * sizeof(double), hipMemcpyHostToDevice, st));
+
+  tem_stats S{};
+  S.n_shifts = J;
+  for (int i = 0; i < 4; ++i) {
+    ctx->prof_ms[i] = 0.0;
+    ctx->prof_n[i] = 0;
+  }
+  S.converged = 1;
+  std::vector<double> f(ctx->n3);
+  std::vector<double> true2(J);
+  int status = TEM_OK;
+  for (int s = 0; s < n_src; ++s) {
+    double2* Y = (double2*)ctx->Y[o.keep_solutions ? s : 0].p;
+    loop_source(ctx, src[s], f);
+    HIPCHK(ctx, hipMemcpyAsync(ctx->f.p, f.data(), ctx->n3 * sizeof(double), hipMemcpyHostToDevice, st));
+    tem::launch_scale(ctx->n3, ctx->d_dinv, (const double*)ctx->f.p, (double*)ctx->gvec.p, st);  // g = M^-1/2 f
+    HIPCHK(ctx, hipGetLastError());
+    SolveState hs;
+    double secs = 0.0;
+    int r = multishift_solve(ctx, sre, sim, s0, o, Y, hs, secs);
+    if (r == TEM_ENOCONV) {
+      S.converged = 0;
+      status = r;
+    } else if (r != TEM_OK) {
+      return r;
+    }
+    S.iterations = hs.k;
+    for (int j = 0; j < J; ++j) {
+      S.iters_per_shift[j] = hs.iters[j];
+      S.est_res[j] = hs.est[j] / std::sqrt(hs.rr0);
+      S.unknown_updates += (double)ctx->nunk * hs.iters[j];
+    }
+    // FP64 true residuals ||g - (A + s_j) y_j|| / ||g|| (the P buffer is free now)
+    tem::launch_to_complex(ctx->n3, (const double*)ctx->gvec.p, (double2*)ctx->gc.p, st);
+    tem::launch_cstencil(ctx->g, Y, ctx->n3, ctx->d_dinv, shd, shd + TEM_MAX_SHIFTS, J, (const double2*)ctx->gc.p,
+                         (double2*)ctx->P.p, ctx->n3, (double*)ctx->cpart.p, st);
+    tem::launch_reduce_rows((const double*)ctx->cpart.p, J, cpb, shd + 2 * TEM_MAX_SHIFTS, st);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipMemcpyAsync(true2.data(), shd + 2 * TEM_MAX_SHIFTS, J * sizeof(double), hipMemcpyDeviceToHost, st));
+    // receivers and (optionally) full fields
+    if (n_rx > 0) {
+      tem::launch_receivers(ctx->g, Y, J, ctx->d_dinv, (const double*)ctx->C.p, T, (const int*)ctx->rx.p, n_rx,
+                            ctx->ks, (double*)ctx->data.p, st);
+      HIPCHK(ctx, hipGetLastError());
+      HIPCHK(ctx, hipMemcpyAsync(data + (size_t)s * T * n_rx, ctx->data.p, (size_t)T * n_rx * sizeof(double),
+                                 hipMemcpyDeviceToHost, st));
+    }
+    if (fields) {
+      tem::launch_contract(ctx->g, Y, J, ctx->d_dinv, (const double*)ctx->C.p, T,
+                           fields + (size_t)s * T * ctx->nstore, st);
+      HIPCHK(ctx, hipGetLastError());
+    }
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    for (int j = 0; j < J; ++j) S.true_res[j] = std::sqrt(true2[j] / hs.rr0);
+  }
+  ctx->fwd_valid = o.keep_solutions != 0;
+  ctx->fwd_J = J;
+  ctx->fwd_T = T;
+  ctx->fwd_nsrc = n_src;
+  ctx->fwd_nrx = n_rx;
+  ctx->fwd_xi.assign(xi, xi + 2 * J);
+  ctx->fwd_c.assign(c, c + 2 * (size_t)J * T);
+  ctx->fwd_rx.assign(rx, rx + n_rx);
+  ctx->fwd_src.assign(src, src + n_src);
+  ctx->fwd_opts = o;
+  S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  for (int i = 0; i < 4; ++i) {
+    S.kernel_ms[i] = ctx->prof_ms[i];
+    S.kernel_launches[i] = ctx->prof_n[i];
+  }
+  if (stats) *stats = S;
+  return status;
+}
+
+int tem_solutions(tem_ctx* ctx, int s, double* X) {
+  if (!ctx) return fail(nullptr, TEM_EINVAL, "ctx is NULL");
+  if (!ctx->fwd_valid) return fail(ctx, TEM_ESTATE, "no stored solutions (run tem_forward with keep_solutions)");
+  if (s < 0 || s >= ctx->fwd_nsrc || !X) return fail(ctx, TEM_EINVAL, "bad source index or NULL output");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  const int J = ctx->fwd_J;
+  DevBuf tmp;
+  int rc;
+  if ((rc = ensure(ctx, tmp, (size_t)J * ctx->nstore * sizeof(double2)))) return rc;
+  tem::launch_gather_solutions(ctx->g, (const double2*)ctx->Y[s].p, J, ctx->d_dinv, (double2*)tmp.p, ctx->stream);
+  hipError_t e = hipMemcpyAsync(X, tmp.p, (size_t)J * ctx->nstore * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  release(tmp);
+  if (e != hipSuccess) return fail(ctx, TEM_EHIP, hipGetErrorString(e));
+  return TEM_OK;
+}
+
+int tem_apply(tem_ctx* ctx, double shift_re, double shift_im, const double* x, double* y) {
+  if (!ctx) return fail(nullptr, TEM_EINVAL, "ctx is NULL");
+  if (!ctx->has_sigma) return fail(ctx, TEM_ESTATE, "conductivity not set");
+  if (!x || !y || !std::isfinite(shift_re) || !std::isfinite(shift_im)) return fail(ctx, TEM_EINVAL, "bad arguments");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  DevBuf xp, xpad, ypad, shv, part;
+  int rc;
+  const size_t sb = ctx->nstore * sizeof(double2), pb = ctx->n3 * sizeof(double2);
+  if ((rc = ensure(ctx, xp, sb)) || (rc = ensure(ctx, xpad, pb)) || (rc = ensure(ctx, ypad, pb)) ||
+      (rc = ensure(ctx, shv, 2 * sizeof(double)))) {
+    release(xp); release(xpad); release(ypad); release(shv);
+    return rc;
+  }
+  const double shh[2] = {shift_re, shift_im};
+  hipError_t e = hipMemcpyAsync(xp.p, x, sb, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(shv.p, shh, sizeof(shh), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    // y = M^1/2 (A + s) M^1/2 x = K x + s M x on interior edges
+    tem::launch_scatter_storage(ctx->g, (const double2*)xp.p, ctx->d_sqrtm, (double2*)xpad.p, st);
+    tem::launch_cstencil(ctx->g, (const double2*)xpad.p, 0, ctx->d_dinv, (const double*)shv.p,
+                         (const double*)shv.p + 1, 1, nullptr, (double2*)ypad.p, 0, nullptr, st);
+    tem::launch_gather_storage(ctx->g, (const double2*)ypad.p, ctx->d_sqrtm, (double2*)xp.p, st);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(y, xp.p, sb, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  release(xp); release(xpad); release(ypad); release(shv); release(part);
+  if (e != hipSuccess) return fail(ctx, TEM_EHIP, hipGetErrorString(e));
+  return TEM_OK;
+}
+
+int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
+  if (!ctx) return fail(nullptr, TEM_EINVAL, "ctx is NULL");
+  (void)w; (void)grad; (void)stats;
+  if (!ctx->fwd_valid) return fail(ctx, TEM_ESTATE, "tem_adjoint needs a preceding tem_forward with keep_solutions");
+  return fail(ctx, TEM_EINVAL, "adjoint not available in this build");
+}
+
+int tem_sizes(const tem_ctx* ctx, long long* n_storage, long long* n_unknowns) {
+  if (!ctx) return fail(nullptr, TEM_EINVAL, "ctx is NULL");
+  if (n_storage) *n_storage = ctx->nstore;
+  if (n_unknowns) *n_unknowns = ctx->nunk;
+  return TEM_OK;
+}
+
+void tem_destroy(tem_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  for (double* p : {ctx->d_axis, ctx->d_sigma, ctx->d_mass, ctx->d_dinv, ctx->d_sqrtm, ctx->d_partials})
+    if (p) hipFree(p);
+  if (ctx->d_state) hipFree(ctx->d_state);
+  if (ctx->d_counters) hipFree(ctx->d_counters);
+  for (DevBuf* b : {&ctx->R, &ctx->pbuf, &ctx->q, &ctx->gvec, &ctx->gc, &ctx->f, &ctx->P, &ctx->C, &ctx->rx,
+                    &ctx->data, &ctx->res, &ctx->cpart, &ctx->sh})
+    release(*b);
+  for (DevBuf& b : ctx->Y) release(b);
+  delete ctx;
+}
+
+const char* tem_last_error(const tem_ctx* ctx) { return ctx ? ctx->err.c_str() : g_global_error.c_str(); }
+
+int tem_poles(int T, const double* t, const double* w, int degree, double tol, int J_max, int* J, double* xi,
+              double* c, double* err) {
+  if (T < 1 || T > 64 || !t || !J || !xi || !c) return fail(nullptr, TEM_EINVAL, "bad arguments to tem_poles");
+  std::vector<double> tv(t, t + T), wv(T, 1.0);
+  for (int k = 0; k < T; ++k)
+    if (!(std::isfinite(tv[k]) && tv[k] > 0.0)) return fail(nullptr, TEM_EINVAL, "channel times must be positive");
+  if (w) {
+    for (int k = 0; k < T; ++k) {
+      if (!(std::isfinite(w[k]) && w[k] > 0.0)) return fail(nullptr, TEM_EINVAL, "weights must be positive");
+      wv[k] = w[k];
+    }
+  }
+  if (degree == 0) {
+    const double ratio = *std::max_element(tv.begin(), tv.end()) / *std::min_element(tv.begin(), tv.end());
+    if (!(tol > 0.0)) return fail(nullptr, TEM_EINVAL, "degree 0 needs a positive tol");
+    degree = tem::table1_degree(ratio, tol);
+    if (degree <= 0) return fail(nullptr, TEM_EINVAL, "no Table 1 degree for this ratio and tolerance");
+  }
+  if (degree < 2 || degree > 2 * TEM_MAX_SHIFTS) return fail(nullptr, TEM_EINVAL, "degree must be in [2, 128]");
+  tem::RkfitResult res;
+  std::string msg;
+  int rc = tem::rkfit(tv, wv, degree, res, msg);
+  if (rc != TEM_OK) return fail(nullptr, rc, msg);
+  const int nJ = (int)res.xi.size();
+  if (nJ > J_max) return fail(nullptr, TEM_EINVAL, "J_max too small for the fitted poles");
+  *J = nJ;
+  for (int j = 0; j < nJ; ++j) {
+    xi[2 * j] = res.xi[j].real();
+    xi[2 * j + 1] = res.xi[j].imag();
+    for (int k = 0; k < T; ++k) {
+      c[2 * ((size_t)j * T + k)] = res.c[(size_t)j * T + k].real();
+      c[2 * ((size_t)j * T + k) + 1] = res.c[(size_t)j * T + k].imag();
+    }
+  }
+  if (err)
+    for (int k = 0; k < T; ++k) err[k] = res.err[k];
+  return TEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,180 @@
+"""GPU parity of the FP64 forward path (C ABI) against the CPU oracle.
+
+Bars (FP64 path):
+  * operator: (K + s M) x by the stencil vs the oracle's assembled CSR,
+    <= 1e-13 relative (pure rounding-order differences);
+  * shifted solutions: per shift ||x_gpu - x_or||_M <= 1e-8 ||x_or||_M;
+  * channels: ||u_gpu(t_k) - u_or(t_k)||_M <= 1e-8 ||u_or(t_k)||_M + 1e-10 S_k and
+    |d_gpu - d_or| <= 1e-8 |d_or| + 1e-10 S^d_k, where S_k = sum_j |c_jk| ||x_j||_M
+    (S^d_k = sum_j |c_jk| |q.x_j|) is the size of the terms of the residue sum:
+    late channels whose value has decayed below the approximation error are
+    cancellation-dominated, and 1e-10 S_k is the attainable floor (two
+    independent direct solvers disagree at that level, see the oracle tests).
+"""
+import numpy as np
+import pytest
+
+import tem_workloads as W
+from oracle import direct, rkfit, yee
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tem():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_11657_amd import tem as T
+    T.lib()
+    return T
+
+
+def _fit(t, m):
+    f = rkfit.rkfit(t, m)
+    s, C = rkfit.shifts_and_coefficients(f)
+    return -s, s, C
+
+
+def _storage_interior(P):
+    return P.idx
+
+
+def test_operator_parity_ragged(tem):
+    rng = np.random.default_rng(7)
+    hx, hy, hz = rng.uniform(5, 30, 37), rng.uniform(5, 30, 11), rng.uniform(5, 30, 9)
+    sigma = 10 ** rng.uniform(-4, 0, (9, 11, 37))
+    wl = W.Workload("op", hx, hy, hz, 4, sigma, loops=[W.Loop(2, 30, 2, 8)], receivers=[], t=np.array([1e-3]))
+    P = yee.Problem(wl)
+    ctx = tem.Context.from_workload(wl)
+    assert ctx.n_storage == P.grid.n_edges and ctx.n_unknowns == P.n
+    for shift in [0.0, 3.5e3 - 2.0e4j, 1e6 + 1e5j]:
+        x = rng.standard_normal(P.grid.n_edges) + 1j * rng.standard_normal(P.grid.n_edges)
+        y = ctx.apply(x, shift)
+        xi = x[P.idx]
+        ref = P.K @ xi + shift * P.M * xi
+        assert np.abs(y[~P.mask]).max() == 0.0
+        err = np.abs(y[P.idx] - ref) / (abs(P.K) @ np.abs(xi) + abs(shift) * P.M * np.abs(xi))
+        assert err.max() < 1e-13
+
+
+def _parity(tem, wl, m, rtol=1e-12, block=32, method="banded"):
+    xi, s, C = _fit(wl.t, m)
+    P = yee.Problem(wl)
+    ctx = tem.Context.from_workload(wl)
+    data, stats = ctx.forward(wl.loops, wl.receivers, xi, C, keep_solutions=True, rtol=rtol, block=block)
+    res = []
+    for src in range(len(wl.loops)):
+        X = ctx.solutions(src)[:, P.idx].T
+        Xo = direct.solve_shifted(P, s, P.F[:, src], method)
+        xn = direct.m_norm(P, Xo)
+        ex = direct.m_norm(P, X - Xo) / xn
+        U, Uo = direct.contract(X, C), direct.contract(Xo, C)
+        Sk = np.abs(C).T @ xn
+        eu = direct.m_norm(P, U - Uo)
+        d_or = (P.Q @ Uo).T
+        Sd = np.abs(C).T @ np.abs(P.Q @ Xo).T
+        ed = np.abs(data[src] - d_or)
+        res.append((ex, eu, direct.m_norm(P, Uo), Sk, ed, np.abs(d_or), Sd))
+    return ctx, stats, res
+
+
+def test_forward_parity_plain16(tem):
+    """The 16^3 plain FP64 configuration (cfg of the benchmark list), degree 38."""
+    wl = W.cfg_plain16()
+    ctx, stats, res = _parity(tem, wl, wl.degree)
+    ex, eu, un, Sk, ed, dn, Sd = res[0]
+    print("iterations", stats["iterations"], "max shift err %.2e" % ex.max(),
+          "true res max %.2e" % max(stats["true_res"]))
+    assert stats["converged"]
+    assert ex.max() <= 1e-8
+    assert np.all(eu <= 1e-8 * un + 1e-10 * Sk)
+    assert np.all(ed <= 1e-8 * dn + 1e-10 * Sd)
+    # resolved channels meet 1e-8 relative outright
+    resolved = Sk <= 100 * un
+    assert resolved.sum() >= 6 and np.all(eu[resolved] <= 1e-8 * un[resolved])
+
+
+def test_forward_parity_ragged_tiles_two_sources(tem):
+    """A grid spanning several stencil tiles with ragged tails in x, y and z,
+    graded widths, random earth, two loop sources and three receivers."""
+    rng = np.random.default_rng(3)
+    hx = rng.uniform(8, 25, 37)
+    hy = rng.uniform(8, 25, 10)
+    hz = rng.uniform(8, 25, 9)
+    sigma = np.full((9, 10, 37), W.SIGMA_AIR)
+    sigma[:5] = 10 ** rng.uniform(-2.5, -0.5, (5, 10, 37))
+    wl = W.Workload("ragged", hx, hy, hz, 5, sigma,
+                    loops=[W.Loop(3, 12, 2, 7, 1.0), W.Loop(20, 33, 3, 8, 2.5)],
+                    receivers=[(7, 4), (25, 5), (30, 1)], t=W.log_channels(1e-5, 1e-3, 12))
+    ctx, stats, res = _parity(tem, wl, 16, method="splu")
+    for ex, eu, un, Sk, ed, dn, Sd in res:
+        assert ex.max() <= 1e-8
+        assert np.all(eu <= 1e-8 * un + 1e-10 * Sk)
+        assert np.all(ed <= 1e-8 * dn + 1e-10 * Sd)
+
+
+def test_fields_mfma_contraction_matches(tem):
+    """Full fields U (storage order, MFMA FP64 contraction) equal Re(X C) of the
+    returned solutions to rounding, and the receivers agree with Q U."""
+    import torch
+    wl = W.small_case(9, seed=5, t=W.log_channels(1e-5, 1e-3, 37))  # 37 channels: 3 column tiles
+    xi, s, C = _fit(wl.t, 22)
+    ctx = tem.Context.from_workload(wl)
+    T = len(wl.t)
+    fields = torch.zeros((1, T, ctx.n_storage), dtype=torch.float64, device="cuda")
+    data, _ = ctx.forward(wl.loops, wl.receivers, xi, C, fields=fields, keep_solutions=True)
+    X = ctx.solutions(0)                       # (J, n_storage)
+    U = fields[0].cpu().numpy()                # (T, n_storage)
+    ref = (C.T @ X).real
+    scale = np.abs(C).T @ np.abs(X)
+    assert np.all(np.abs(U - ref) <= 1e-13 * scale + 1e-300)
+    P = yee.Problem(wl)
+    q = P.grid.receiver_row_full(*wl.receivers[0], wl.k_s)
+    dq = U @ q
+    assert np.allclose(data[0, :, 0], dq, rtol=1e-11, atol=1e-13 * np.abs(scale @ np.abs(q)).max())
+
+
+def test_bitwise_repeatable(tem):
+    wl = W.small_case(8, seed=2, t=W.log_channels(1e-5, 1e-3, 8))
+    xi, s, C = _fit(wl.t, 16)
+    ctx = tem.Context.from_workload(wl)
+    d1, _ = ctx.forward(wl.loops, wl.receivers, xi, C, keep_solutions=True)
+    X1 = ctx.solutions(0)
+    d2, _ = ctx.forward(wl.loops, wl.receivers, xi, C, keep_solutions=True)
+    X2 = ctx.solutions(0)
+    assert np.array_equal(d1, d2) and np.array_equal(X1, X2)
+
+
+def test_block_length_does_not_change_result(tem):
+    """Deferred shift updates every B iterations are the same recurrence: B = 8,
+    16, 32, 64 agree to rounding."""
+    wl = W.small_case(8, seed=4, t=W.log_channels(1e-5, 1e-3, 8))
+    xi, s, C = _fit(wl.t, 16)
+    ctx = tem.Context.from_workload(wl)
+    base = None
+    for B in (8, 16, 32, 64):
+        d, st = ctx.forward(wl.loops, wl.receivers, xi, C, block=B, keep_solutions=True)
+        X = ctx.solutions(0)
+        if base is None:
+            base = X
+        else:
+            assert np.abs(X - base).max() <= 1e-10 * np.abs(base).max()
+
+
+def test_noconv_and_errors(tem):
+    wl = W.small_case(6, seed=1, t=W.log_channels(1e-5, 1e-3, 6))
+    xi, s, C = _fit(wl.t, 12)
+    ctx = tem.Context.from_workload(wl)
+    d, st = ctx.forward(wl.loops, wl.receivers, xi, C, max_iter=8, allow_noconv=True)
+    assert st["status"] == "TEM_ENOCONV" and not st["converged"]
+    with pytest.raises(tem.TemError) as e:
+        ctx.forward([(0, 3, 1, 3, 1.0)], wl.receivers, xi, C)
+    assert e.value.status == tem.TEM_EINVAL
+    with pytest.raises(tem.TemError) as e:
+        ctx.adjoint(np.zeros((1, 6, 1)))
+    assert e.value.status == tem.TEM_ESTATE
+    bad = wl.sigma.copy()
+    bad[0, 0, 0] = -1.0
+    with pytest.raises(tem.TemError):
+        ctx.set_conductivity(bad)
