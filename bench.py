@@ -41,6 +41,17 @@ def algorithmic_bytes(kind, ctx_dims, J_apply, B):
     return (8.0 * B + 64.0 * J_apply) * padded
 
 
+# HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE runs, keyed by the
+# kernel source it was measured on (bytes per launch; see profiles/); None once the source changes
+TRAFFIC = {("5df450facc16", "graded64", "seed_stencil"): (16802.6 + 12592.1) * 1024.0}
+
+
+def kernel_source_hash():
+    import hashlib
+    p = os.path.join(ROOT, "paper_2506_11657_amd", "csrc", "tem_kernels.hip")
+    return hashlib.sha1(open(p, "rb").read()).hexdigest()[:12]
+
+
 def cpu_baseline(wl, s, seconds):
     """The oracle's plain CSR multi-shift CG on the same problem, bounded in time."""
     from oracle import mscg, yee
@@ -132,7 +143,8 @@ def main():
         "true_res_max": max(last["true_res"]),
         "kernel_ms_per_step": {names[i]: ms[i] for i in range(3)},
         "roofline": {"bound": "hbm", "kernel": names[kind], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": TRAFFIC.get((kernel_source_hash(), wl.name, names[kind])),
                      "avg_launch_us": 1e6 * avg_s, "algorithmic_bytes_per_launch": nbytes},
     }
     if not args.no_cpu:

@@ -76,7 +76,7 @@ typedef struct {
   int precision;     /* 0: FP64 Krylov sweeps; 1: FP32 sweeps + FP64 residual refinement */
   double rtol;       /* per-shift stop: |zeta_j| ||r||_2 <= rtol ||g||_2 in the scaled system;
                         <= 0 selects 1e-12 (FP64) */
-  int max_iter;      /* cap on seed iterations per solve; <= 0 selects 200000 */
+  int max_iter;      /* cap on seed iterations per solve; <= 0 selects 2000000 */
   int block;         /* iterations between deferred shift updates (1..64); <= 0 selects 32 */
   double seed_shift; /* real seed shift of the shared recurrence; <= 0 selects
                         max(min_j Re s_j, 1e-3 min_j |s_j|), s_j = -xi_j */

@@ -14,6 +14,7 @@
 
 using tem::GridArgs;
 using tem::SolveState;
+static_assert(sizeof(tem::SolveHead) <= 4096, "pinned head buffer");
 
 namespace {
 
@@ -28,7 +29,10 @@ struct DevBuf {
 
 struct tem_ctx {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;       // caller's stream (may be the null stream)
+  hipStream_t work = nullptr;         // library-owned stream: every kernel runs here
+  hipEvent_t order_ev = nullptr;      // orders work after the caller's stream
+  void* head_pinned = nullptr;        // pinned host copy of the solver head
   int nx = 0, ny = 0, nz = 0, ks = 0;
   std::vector<double> hx, hy, hz;
   GridArgs g{};
@@ -85,7 +89,7 @@ int ensure(tem_ctx* ctx, DevBuf& b, size_t bytes) {
     (void)hipGetLastError();
     return fail(ctx, TEM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   }
-  if (hipMemsetAsync(b.p, 0, bytes, ctx->stream) != hipSuccess)
+  if (hipMemsetAsync(b.p, 0, bytes, ctx->work) != hipSuccess)
     return fail(ctx, TEM_EHIP, "hipMemsetAsync failed");
   b.bytes = bytes;
   return TEM_OK;
@@ -133,11 +137,18 @@ int check_loops(tem_ctx* ctx, const tem_loop* src, int n_src) {
   return TEM_OK;
 }
 
+// Make the library stream wait for everything already queued on the caller's stream.
+int order_after_caller(tem_ctx* ctx) {
+  HIPCHK(ctx, hipEventRecord(ctx->order_ev, ctx->stream));
+  HIPCHK(ctx, hipStreamWaitEvent(ctx->work, ctx->order_ev, 0));
+  return TEM_OK;
+}
+
 tem_solve_opts resolve_opts(const tem_solve_opts* o) {
   tem_solve_opts r{};
   if (o) r = *o;
   if (!(r.rtol > 0.0)) r.rtol = 1e-12;
-  if (r.max_iter <= 0) r.max_iter = 200000;
+  if (r.max_iter <= 0) r.max_iter = 2000000;
   if (r.block <= 0) r.block = 32;
   if (r.refine_max <= 0) r.refine_max = 8;
   return r;
@@ -156,9 +167,10 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
                      double s0, const tem_solve_opts& o, double2* Y, SolveState& host_state, double& seconds) {
   const int J = (int)shifts_re.size();
   const int B = block_length(o.block, J);
-  hipStream_t st = ctx->stream;
+  hipStream_t st = ctx->work;
   const GridArgs& g = ctx->g;
   int rc;
+  (void)st;
   if ((rc = ensure(ctx, ctx->R, (size_t)B * ctx->n3 * sizeof(double)))) return rc;
   if ((rc = ensure(ctx, ctx->pbuf, 2 * ctx->n3 * sizeof(double)))) return rc;
   if ((rc = ensure(ctx, ctx->q, ctx->n3 * sizeof(double)))) return rc;
@@ -176,7 +188,7 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
   for (int j = 0; j < J; ++j) {
     hs->sig_re[j] = shifts_re[j] - s0;
     hs->sig_im[j] = shifts_im[j];
-    hs->z_re[j] = hs->zp_re[j] = 1.0;
+    hs->z_re[j] = hs->zp_re[j] = 1.0;  // zeta_0 = zeta_{-1} = 1
     hs->active[j] = 1;
     hs->apply[j] = 1;
     hs->a_re[j] = 1.0;
@@ -188,42 +200,69 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
   tem::launch_seed_init(g, (const double*)ctx->gvec.p, R, pb + ctx->n3, Y, P, J, red, ctx->d_state, st);
   HIPCHK(ctx, hipGetLastError());
 
-  struct Head {
-    double rr, rr0, pAp, alpha, beta, alpha_prev, beta_prev, tol2;
-    int k, n_active, breakdown;
-  } head{};
-  // optional per-launch timing: one event pair per launch of the block
+  tem::SolveHead head{};
+  // One block of B seed iterations plus the deferred shift update is the same
+  // launch sequence every time (slots depend on k mod B only), so it is
+  // captured once into a HIP graph and replayed; with opts.profile the
+  // launches are issued directly with an event pair around each.
+  auto launch_block = [&](bool timed, std::vector<hipEvent_t>& ev) {
+    for (int i = 0; i < B; ++i) {
+      double* r = R + (size_t)i * ctx->n3;
+      double* rn = R + (size_t)((i + 1) % B) * ctx->n3;
+      double* pold = pb + (size_t)((i + 1) & 1) * ctx->n3;
+      double* pnew = pb + (size_t)(i & 1) * ctx->n3;
+      if (timed) (void)hipEventRecord(ev[4 * i], st);
+      tem::launch_seed_stencil(g, r, pold, pnew, q, ctx->d_dinv, s0, red, ctx->d_state, i, st);
+      if (timed) (void)hipEventRecord(ev[4 * i + 1], st);
+      if (timed) (void)hipEventRecord(ev[4 * i + 2], st);
+      tem::launch_seed_update(g, r, q, rn, red, ctx->d_state, i, st);
+      if (timed) (void)hipEventRecord(ev[4 * i + 3], st);
+    }
+    if (timed) (void)hipEventRecord(ev[4 * B], st);
+    tem::launch_shift_block(g, J, red, ctx->d_state, st);
+    tem::launch_block_update(g, R, Y, P, J, B, ctx->d_state, st);
+    if (timed) (void)hipEventRecord(ev[4 * B + 1], st);
+  };
   std::vector<hipEvent_t> ev;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
   if (o.profile) {
     ev.resize(2 * (2 * B + 1));
     for (auto& e : ev) HIPCHK(ctx, hipEventCreate(&e));
   }
-  auto mark = [&](int slot) {
-    if (o.profile) (void)hipEventRecord(ev[slot], st);
-  };
+  // with profiling, one block in kProfileEvery is issued directly with an
+  // event pair around each launch (sampling the kernel times inside the timed
+  // solve); every other block is a replay of the captured graph
+  constexpr int kProfileEvery = 16;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    launch_block(false, ev);
+    hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (ce == hipSuccess) ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ce != hipSuccess) {
+      (void)hipGetLastError();
+      if (graph) (void)hipGraphDestroy(graph);
+      graph = nullptr;
+      exec = nullptr;
+    }
+  } else {
+    (void)hipGetLastError();
+  }
+  tem::SolveHead* hp = (tem::SolveHead*)ctx->head_pinned;
   int k = 0;
   bool done = false;
-  int rc_loop = TEM_OK;
+  hipError_t lerr = hipSuccess;
+  int nblock = 0;
   while (!done && k < o.max_iter) {
-    for (int i = 0; i < B; ++i, ++k) {
-      double* r = R + (size_t)(k % B) * ctx->n3;
-      double* rn = R + (size_t)((k + 1) % B) * ctx->n3;
-      double* pold = pb + (size_t)((k + 1) & 1) * ctx->n3;
-      double* pnew = pb + (size_t)(k & 1) * ctx->n3;
-      mark(4 * i);
-      tem::launch_seed_stencil(g, r, pold, pnew, q, ctx->d_dinv, s0, red, ctx->d_state, st);
-      mark(4 * i + 1);
-      mark(4 * i + 2);
-      tem::launch_seed_update(g, r, q, rn, red, ctx->d_state, (k + 1) % B, st);
-      mark(4 * i + 3);
-    }
-    mark(4 * B);
-    tem::launch_block_update(g, R, Y, P, J, B, ctx->d_state, st);
-    mark(4 * B + 1);
-    HIPCHK(ctx, hipGetLastError());
-    HIPCHK(ctx, hipMemcpyAsync(&head, ctx->d_state, sizeof(Head), hipMemcpyDeviceToHost, st));
-    HIPCHK(ctx, hipStreamSynchronize(st));
-    if (o.profile) {
+    const bool sample = o.profile && (nblock++ % kProfileEvery == 0);
+    if (exec && !sample) lerr = hipGraphLaunch(exec, st);
+    else launch_block(sample, ev);
+    if (lerr == hipSuccess) lerr = hipGetLastError();
+    if (lerr == hipSuccess) lerr = hipMemcpyAsync(hp, ctx->d_state, sizeof(tem::SolveHead), hipMemcpyDeviceToHost, st);
+    if (lerr == hipSuccess) lerr = hipStreamSynchronize(st);
+    if (lerr != hipSuccess) break;
+    k += B;
+    head = *hp;
+    if (sample) {
       for (int i = 0; i < B; ++i) {
         float a = 0.f, b = 0.f;
         (void)hipEventElapsedTime(&a, ev[4 * i], ev[4 * i + 1]);
@@ -239,15 +278,20 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
       ctx->prof_n[TEM_K_BLOCK] += 1;
     }
     if (head.breakdown) break;
-    if (head.n_active == 0) done = true;
+    int n_active = 0;
+    for (int j = 0; j < J; ++j) n_active += head.active[j];
+    if (n_active == 0) done = true;
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
-  (void)rc_loop;
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (lerr != hipSuccess) return fail(ctx, TEM_EHIP, std::string("solver loop: ") + hipGetErrorString(lerr));
   seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   HIPCHK(ctx, hipMemcpyAsync(&host_state, ctx->d_state, sizeof(SolveState), hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipStreamSynchronize(st));
   if (host_state.breakdown) return fail(ctx, TEM_EBREAKDOWN, "Krylov breakdown in the shared recurrence");
-  if (host_state.n_active > 0) return fail(ctx, TEM_ENOCONV, "max_iter reached before every shift converged");
+  for (int j = 0; j < J; ++j)
+    if (host_state.active[j]) return fail(ctx, TEM_ENOCONV, "max_iter reached before every shift converged");
   return TEM_OK;
 }
 
@@ -288,6 +332,7 @@ int tem_setup_grid(tem_ctx** out, int nx, int ny, int nz, const double* hx, cons
   g.nn = (long long)g.px * g.py * g.pz;
   c->n3 = 3 * g.nn;
   c->nstore = tem::storage_edges(g);
+  if (tem::seed_stencil_blocks(g) > tem::kReduceSlots) return fail(nullptr, TEM_EINVAL, "grid too large for this build");
   c->nunk = (long long)nx * (ny - 1) * (nz - 1) + (long long)(nx - 1) * ny * (nz - 1) + (long long)(nx - 1) * (ny - 1) * nz;
   // axis arrays: h, 1/h, dual/mu0 per axis, each padded to n+1
   const int L = std::max(nx, std::max(ny, nz)) + 1;
@@ -325,6 +370,9 @@ int tem_setup_grid(tem_ctx** out, int nx, int ny, int nz, const double* hx, cons
   HIPCHK(ctx, hipMalloc(&c->d_partials, 2 * tem::kReduceSlots * sizeof(double)));
   HIPCHK(ctx, hipMalloc(&c->d_counters, 16 * sizeof(unsigned int)));
   HIPCHK(ctx, hipMemset(c->d_counters, 0, 16 * sizeof(unsigned int)));
+  HIPCHK(ctx, hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking));
+  HIPCHK(ctx, hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming));
+  HIPCHK(ctx, hipHostMalloc(&c->head_pinned, 4096, hipHostMallocDefault));
   *out = c.release();
   return TEM_OK;
 }
@@ -347,10 +395,11 @@ int tem_set_conductivity(tem_ctx* ctx, const double* sigma, int flags) {
     }
     if (!(std::isfinite(h[i]) && h[i] > 0.0)) return fail(ctx, TEM_EINVAL, "sigma must be finite and positive");
   }
-  HIPCHK(ctx, hipMemcpyAsync(ctx->d_sigma, h.data(), ncell * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-  tem::launch_mass(ctx->g, ctx->d_sigma, ctx->d_mass, ctx->d_dinv, ctx->d_sqrtm, ctx->stream);
+  if (int rc = order_after_caller(ctx)) return rc;
+  HIPCHK(ctx, hipMemcpyAsync(ctx->d_sigma, h.data(), ncell * sizeof(double), hipMemcpyHostToDevice, ctx->work));
+  tem::launch_mass(ctx->g, ctx->d_sigma, ctx->d_mass, ctx->d_dinv, ctx->d_sqrtm, ctx->work);
   HIPCHK(ctx, hipGetLastError());
-  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->work));
   ctx->has_sigma = true;
   ctx->fwd_valid = false;
   return TEM_OK;
@@ -391,7 +440,8 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
     }
     s0 = std::max(minre, 1e-3 * minabs);
   }
-  hipStream_t st = ctx->stream;
+  if ((rc = order_after_caller(ctx))) return rc;
+  hipStream_t st = ctx->work;
   const size_t ysz = (size_t)J * ctx->n3 * sizeof(double2);
   const int nY = o.keep_solutions ? n_src : 1;
   if ((int)ctx->Y.size() < nY) ctx->Y.resize(nY);
@@ -499,9 +549,9 @@ int tem_solutions(tem_ctx* ctx, int s, double* X) {
   DevBuf tmp;
   int rc;
   if ((rc = ensure(ctx, tmp, (size_t)J * ctx->nstore * sizeof(double2)))) return rc;
-  tem::launch_gather_solutions(ctx->g, (const double2*)ctx->Y[s].p, J, ctx->d_dinv, (double2*)tmp.p, ctx->stream);
-  hipError_t e = hipMemcpyAsync(X, tmp.p, (size_t)J * ctx->nstore * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  tem::launch_gather_solutions(ctx->g, (const double2*)ctx->Y[s].p, J, ctx->d_dinv, (double2*)tmp.p, ctx->work);
+  hipError_t e = hipMemcpyAsync(X, tmp.p, (size_t)J * ctx->nstore * sizeof(double2), hipMemcpyDeviceToHost, ctx->work);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->work);
   release(tmp);
   if (e != hipSuccess) return fail(ctx, TEM_EHIP, hipGetErrorString(e));
   return TEM_OK;
@@ -512,7 +562,8 @@ int tem_apply(tem_ctx* ctx, double shift_re, double shift_im, const double* x, d
   if (!ctx->has_sigma) return fail(ctx, TEM_ESTATE, "conductivity not set");
   if (!x || !y || !std::isfinite(shift_re) || !std::isfinite(shift_im)) return fail(ctx, TEM_EINVAL, "bad arguments");
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  hipStream_t st = ctx->stream;
+  if (int rc0 = order_after_caller(ctx)) return rc0;
+  hipStream_t st = ctx->work;
   DevBuf xp, xpad, ypad, shv, part;
   int rc;
   const size_t sb = ctx->nstore * sizeof(double2), pb = ctx->n3 * sizeof(double2);
@@ -540,10 +591,113 @@ int tem_apply(tem_ctx* ctx, double shift_re, double shift_im, const double* x, d
 }
 
 int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
+  auto t_start = std::chrono::steady_clock::now();
   if (!ctx) return fail(nullptr, TEM_EINVAL, "ctx is NULL");
-  (void)w; (void)grad; (void)stats;
   if (!ctx->fwd_valid) return fail(ctx, TEM_ESTATE, "tem_adjoint needs a preceding tem_forward with keep_solutions");
-  return fail(ctx, TEM_EINVAL, "adjoint not available in this build");
+  if (!w || !grad) return fail(ctx, TEM_EINVAL, "w and grad must not be NULL");
+  const int J = ctx->fwd_J, T = ctx->fwd_T, n_rx = ctx->fwd_nrx, n_src = ctx->fwd_nsrc;
+  if (n_rx < 1) return fail(ctx, TEM_EINVAL, "the forward had no receivers");
+  for (long long i = 0; i < (long long)n_src * T * n_rx; ++i)
+    if (!std::isfinite(w[i])) return fail(ctx, TEM_EINVAL, "non-finite w");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  int rc;
+  if ((rc = order_after_caller(ctx))) return rc;
+  hipStream_t st = ctx->work;
+  const tem_solve_opts& o = ctx->fwd_opts;
+  const size_t vb = (size_t)J * ctx->n3 * sizeof(double2);
+  DevBuf H, Mu, Rr, Pb, Q, z, gd, gam, cst, part;
+  auto cleanup = [&]() {
+    for (DevBuf* b : {&H, &Mu, &Rr, &Pb, &Q, &z, &gd, &gam, &cst, &part}) release(*b);
+  };
+  const long long ncell = (long long)ctx->nx * ctx->ny * ctx->nz;
+  if ((rc = ensure(ctx, H, vb)) || (rc = ensure(ctx, Mu, vb)) || (rc = ensure(ctx, Rr, vb)) ||
+      (rc = ensure(ctx, Pb, 2 * vb)) || (rc = ensure(ctx, Q, vb)) || (rc = ensure(ctx, z, ctx->n3 * sizeof(double))) ||
+      (rc = ensure(ctx, gd, ncell * sizeof(double))) || (rc = ensure(ctx, gam, 2 * (size_t)J * n_rx * sizeof(double))) ||
+      (rc = ensure(ctx, cst, tem::cocg_state_bytes())) ||
+      (rc = ensure(ctx, part, (size_t)tem::cocg_partials(ctx->g, J) * sizeof(double)))) {
+    cleanup();
+    return rc;
+  }
+  // shifts s_j = -xi_j on the device (sh buffer of the forward holds them)
+  double* shd = (double*)ctx->sh.p;
+  std::unique_ptr<tem::CocgState> hs(new tem::CocgState());
+  tem_stats S{};
+  S.n_shifts = J;
+  S.converged = 1;
+  std::vector<double> gamma(2 * (size_t)J * n_rx);
+  const double* C = ctx->fwd_c.data();
+  hipError_t e = hipSuccess;
+  for (int s = 0; s < n_src && e == hipSuccess; ++s) {
+    // gamma_jr = sum_k c_jk w[s][k][r]  (the adjoint source g_j = sum_r gamma_jr q_r)
+    for (int j = 0; j < J; ++j)
+      for (int r = 0; r < n_rx; ++r) {
+        double gr = 0.0, gi = 0.0;
+        for (int k = 0; k < T; ++k) {
+          const double wk = w[((size_t)s * T + k) * n_rx + r];
+          gr += C[2 * ((size_t)j * T + k)] * wk;
+          gi += C[2 * ((size_t)j * T + k) + 1] * wk;
+        }
+        gamma[2 * ((size_t)j * n_rx + r)] = gr;
+        gamma[2 * ((size_t)j * n_rx + r) + 1] = gi;
+      }
+    e = hipMemcpyAsync(gam.p, gamma.data(), gamma.size() * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(H.p, 0, vb, st);
+    std::memset(hs.get(), 0, sizeof(tem::CocgState));
+    hs->J = J;
+    hs->tol2 = o.rtol * o.rtol;
+    if (e == hipSuccess) e = hipMemcpyAsync(cst.p, hs.get(), sizeof(tem::CocgState), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->d_counters + 4, 0, 4 * sizeof(unsigned int), st);
+    if (e != hipSuccess) break;
+    tem::launch_adj_rhs(ctx->g, J, n_rx, (const int*)ctx->rx.p, ctx->ks, (const double*)gam.p, ctx->d_dinv,
+                        (double2*)H.p, st);
+    double2* P0 = (double2*)Pb.p;
+    double2* P1 = P0 + (size_t)J * ctx->n3;
+    double* partials = (double*)part.p;
+    tem::launch_cocg_init(ctx->g, J, (const double2*)H.p, (double2*)Mu.p, (double2*)Rr.p, P0, partials,
+                          ctx->d_counters + 4, cst.p, st);
+    int it = 0;
+    const int chunk = 32;
+    while (e == hipSuccess && it < o.max_iter) {
+      for (int i = 0; i < chunk; ++i, ++it) {
+        double2* Pold = (it & 1) ? P1 : P0;
+        double2* Pnew = (it & 1) ? P0 : P1;
+        tem::launch_cocg_stencil(ctx->g, J, (const double2*)Rr.p, Pold, Pnew, (double2*)Q.p, ctx->d_dinv, shd,
+                                 shd + TEM_MAX_SHIFTS, partials, ctx->d_counters + 5, cst.p, st);
+        tem::launch_cocg_update(ctx->g, J, (double2*)Mu.p, (double2*)Rr.p, Pnew, (const double2*)Q.p, partials,
+                                ctx->d_counters + 6, cst.p, st);
+      }
+      e = hipGetLastError();
+      if (e == hipSuccess) e = hipMemcpyAsync(hs.get(), cst.p, sizeof(tem::CocgState), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) break;
+      S.iterations = it;
+      if (hs->breakdown) {
+        cleanup();
+        return fail(ctx, TEM_EBREAKDOWN, "COCG breakdown in the adjoint solves");
+      }
+      if (hs->n_active == 0) break;
+    }
+    if (e != hipSuccess) break;
+    if (hs->n_active > 0) S.converged = 0;
+    for (int j = 0; j < J; ++j) {
+      S.iters_per_shift[j] = hs->iters[j];
+      S.est_res[j] = hs->hn2[j] > 0 ? std::sqrt(hs->rn2[j] / hs->hn2[j]) : 0.0;
+      S.unknown_updates += (double)ctx->nunk * hs->iters[j];
+    }
+    tem::launch_grad_edges(ctx->g, J, (const double2*)Mu.p, (const double2*)ctx->Y[s].p, ctx->d_dinv, shd,
+                           shd + TEM_MAX_SHIFTS, (double*)z.p, st);
+  }
+  if (e == hipSuccess) {
+    tem::launch_grad_cells(ctx->g, ctx->d_sigma, (const double*)z.p, (double*)gd.p, st);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(grad, gd.p, ncell * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  cleanup();
+  if (e != hipSuccess) return fail(ctx, TEM_EHIP, std::string("adjoint: ") + hipGetErrorString(e));
+  S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  if (stats) *stats = S;
+  return S.converged ? TEM_OK : fail(ctx, TEM_ENOCONV, "adjoint COCG did not reach rtol within max_iter");
 }
 
 int tem_sizes(const tem_ctx* ctx, long long* n_storage, long long* n_unknowns) {
@@ -556,7 +710,7 @@ int tem_sizes(const tem_ctx* ctx, long long* n_storage, long long* n_unknowns) {
 void tem_destroy(tem_ctx* ctx) {
   if (!ctx) return;
   hipSetDevice(ctx->device);
-  hipStreamSynchronize(ctx->stream);
+  if (ctx->work) hipStreamSynchronize(ctx->work);
   for (double* p : {ctx->d_axis, ctx->d_sigma, ctx->d_mass, ctx->d_dinv, ctx->d_sqrtm, ctx->d_partials})
     if (p) hipFree(p);
   if (ctx->d_state) hipFree(ctx->d_state);
@@ -565,6 +719,9 @@ void tem_destroy(tem_ctx* ctx) {
                     &ctx->data, &ctx->res, &ctx->cpart, &ctx->sh})
     release(*b);
   for (DevBuf& b : ctx->Y) release(b);
+  if (ctx->head_pinned) hipHostFree(ctx->head_pinned);
+  if (ctx->order_ev) hipEventDestroy(ctx->order_ev);
+  if (ctx->work) hipStreamDestroy(ctx->work);
   delete ctx;
 }
 

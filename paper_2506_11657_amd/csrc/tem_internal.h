@@ -14,7 +14,7 @@ namespace tem {
 constexpr double kMu0 = 4e-7 * 3.14159265358979323846;  // Sec. 2.1
 constexpr int kMaxShifts = 64;
 constexpr int kMaxBlock = 64;       // deferred-update block length (iterations)
-constexpr int kReduceSlots = 4096;  // per-kernel partial sums (upper bound on blocks)
+constexpr int kReduceSlots = 65536;  // per-kernel partial sums (upper bound on stencil blocks)
 
 // Node-padded layout: every node (i, j, k), 0 <= i <= nx, ... owns the three
 // edges Ex(i,j,k), Ey(i,j,k), Ez(i,j,k) leaving it in +x, +y, +z.  Edges that
@@ -30,25 +30,29 @@ struct GridArgs {
   const double* dw[3];      // dual width / mu0 per node, length n_a + 1
 };
 
-// Seed-recurrence scalars and per-shift state; lives in device memory and is
-// updated only by the single "last" workgroup of a kernel.
+// Seed-recurrence scalars and per-shift state; lives in device memory.  The
+// seed kernels touch only the seed scalars and the per-iteration history;
+// the per-shift recurrences are replayed from that history once per block.
 struct SolveState {
-  double rr;          // (r_k, r_k)
-  double rr0;         // (g, g)
-  double pAp;         // (p_k, A0 p_k)
-  double alpha, beta; // seed alpha_k, beta_k
-  double alpha_prev, beta_prev;
-  double tol2;        // (rtol * ||g||)^2
-  int k;              // seed iteration counter
-  int n_active;
+  // --- read back by the host after every block (keep first) ---
+  int k;              // seed iterations done
   int breakdown;
   int J;
   int B;              // block length
-  int pad_;
+  int active[kMaxShifts];
+  // --- seed scalars ---
+  double rr;          // (r_k, r_k)
+  double rr0;         // (g, g)
+  double pAp;         // (p_k, A0 p_k)
+  double alpha, beta; // alpha_k, beta_k of the last completed steps
+  double tol2;        // (rtol ||g||)^2
+  double alpha_h[kMaxBlock], beta_h[kMaxBlock], rr_h[kMaxBlock];  // this block's alpha_k, beta_k, (r_{k+1}, r_{k+1})
+  double carry_alpha, carry_beta;                                 // alpha, beta of the step before the block
+  double rrk[2];                                                  // (r_k, r_k) by parity of k
+  // --- per shift ---
   double sig_re[kMaxShifts], sig_im[kMaxShifts];    // s_j - s0
   double z_re[kMaxShifts], z_im[kMaxShifts];        // zeta_k
   double zp_re[kMaxShifts], zp_im[kMaxShifts];      // zeta_{k-1}
-  int active[kMaxShifts];
   int apply[kMaxShifts];                            // updated at least once in this block
   int iters[kMaxShifts];
   double est[kMaxShifts];                           // |zeta| ||r|| at the stop
@@ -57,6 +61,26 @@ struct SolveState {
   double c_re[kMaxShifts], c_im[kMaxShifts];
   double d_re[kMaxShifts][kMaxBlock], d_im[kMaxShifts][kMaxBlock];
   double e_re[kMaxShifts][kMaxBlock], e_im[kMaxShifts][kMaxBlock];
+};
+
+struct SolveHead {  // the leading part of SolveState
+  int k, breakdown, J, B;
+  int active[kMaxShifts];
+};
+
+// Batched COCG state (adjoint and refinement solves), device memory.
+struct CocgState {
+  double rho_re[kMaxShifts], rho_im[kMaxShifts];  // r^T r
+  double alpha_re[kMaxShifts], alpha_im[kMaxShifts];
+  double beta_re[kMaxShifts], beta_im[kMaxShifts];
+  double hn2[kMaxShifts];                          // |rhs|^2
+  double rn2[kMaxShifts];                          // |r|^2
+  double tol2;                                     // rtol^2 (set by the host)
+  int active[kMaxShifts];
+  int iters[kMaxShifts];
+  int n_active;
+  int breakdown;
+  int J;                                           // set by the host
 };
 
 struct Reduce {
@@ -72,11 +96,12 @@ void launch_to_complex(long long n, const double* x, double2* y, hipStream_t s);
 void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, double2* Y, double2* P,
                       int J, Reduce red, SolveState* st, hipStream_t s);
 void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold, double* pnew, double* q,
-                         const double* dinv, double s0, Reduce red, SolveState* st, hipStream_t s);
+                         const double* dinv, double s0, Reduce red, SolveState* st, int local, hipStream_t s);
 void launch_seed_update(const GridArgs& g, const double* r, const double* q, double* rnext, Reduce red,
-                        SolveState* st, int slot_next, hipStream_t s);
+                        SolveState* st, int local, hipStream_t s);
 void launch_block_update(const GridArgs& g, const double* R, double2* Y, double2* P, int J, int B,
                          const SolveState* st, hipStream_t s);
+void launch_shift_block(const GridArgs& g, int J, Reduce red, SolveState* st, hipStream_t s);
 void launch_cstencil(const GridArgs& g, const double2* X, long long xstride, const double* dinv,
                      const double* shift_re, const double* shift_im, int nvec, const double2* rhs,
                      double2* out, long long ostride, double* norm_partials, hipStream_t s);
@@ -92,6 +117,22 @@ void launch_gather_storage(const GridArgs& g, const double2* xpad, const double*
 long long storage_edges(const GridArgs& g);
 int cstencil_partials(const GridArgs& g);
 int reduce_blocks(long long n);
+int seed_stencil_blocks(const GridArgs& g);
+// adjoint: batched COCG (state is an opaque device struct of cocg_state_bytes())
+size_t cocg_state_bytes();
+int cocg_partials(const GridArgs& g, int J);
+void launch_adj_rhs(const GridArgs& g, int J, int n_rx, const int* rx, int ks, const double* gamma, const double* dinv,
+                    double2* H, hipStream_t s);
+void launch_cocg_init(const GridArgs& g, int J, const double2* H, double2* Mu, double2* Rr, double2* Pold,
+                      double* partials, unsigned int* counter, void* st, hipStream_t s);
+void launch_cocg_stencil(const GridArgs& g, int J, const double2* Rr, const double2* Pold, double2* Pnew, double2* Q,
+                         const double* dinv, const double* sre, const double* sim, double* partials,
+                         unsigned int* counter, void* st, hipStream_t s);
+void launch_cocg_update(const GridArgs& g, int J, double2* Mu, double2* Rr, const double2* Pn, const double2* Q,
+                        double* partials, unsigned int* counter, void* st, hipStream_t s);
+void launch_grad_edges(const GridArgs& g, int J, const double2* Mu, const double2* Y, const double* dinv,
+                       const double* sre, const double* sim, double* z, hipStream_t s);
+void launch_grad_cells(const GridArgs& g, const double* sigma, const double* z, double* grad, hipStream_t s);
 
 // ---- host RKFIT (tem_rkfit.cpp) --------------------------------------------
 struct RkfitResult {

@@ -6,6 +6,8 @@
 //     (A + s_j) y_j = g,   A = M^{-1/2} K M^{-1/2},   g = M^{-1/2} f,
 // where K = C^T W C is applied matrix-free: face circulations of the scaled
 // field weighted by h_dual / (mu0 * area), then gathered back onto the edges.
+#include <cstdlib>
+
 #include "tem_internal.h"
 
 namespace tem {
@@ -125,17 +127,39 @@ __device__ __forceinline__ int storage_to_node(const GridArgs& g, long long e, l
 // ---------------------------------------------------------------------------
 template <typename Val, int TX, int TY, int KZ, typename LoadFn, typename EmitFn>
 __device__ void stencil_tile(const GridArgs& g, const double* __restrict__ dinv, int zb, LoadFn load, EmitFn emit) {
-  __shared__ Val sp[2][3][TY + 2][TX + 2];  // scaled field, two planes
-  __shared__ Val phi[3][TY + 1][TX + 1];    // face fluxes of the current plane
+  __shared__ Val sp[2][3][TY + 2][TX + 2];     // scaled field dinv * u, two planes
+  __shared__ Val su[2][3][TY + 2][TX + 2];     // unscaled field u
+  __shared__ double sd[2][3][TY + 2][TX + 2];  // dinv
+  __shared__ Val phi[3][TY + 1][TX + 1];       // face fluxes of the current plane
 
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = tx + TX * ty;
   constexpr int NT = TX * TY;
+  constexpr int NF = ((TX + 1) * (TY + 1) + NT - 1) / NT;  // flux entries per thread
   const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
   const int k0 = zb * KZ;
   const int kend = min(k0 + KZ, g.nz);
   const int i = i0 + tx, j = j0 + ty;
   const bool own = (i < g.nx) && (j < g.ny);
+
+  // per-thread horizontal weights of the flux entries it computes (fixed over the march)
+  double fhx[NF], fhy[NF], fwx[NF], fwy[NF], fwz[NF];
+  int fgi[NF], fgj[NF];
+#pragma unroll
+  for (int q = 0; q < NF; ++q) {
+    const int e = tid + q * NT;
+    const int li = e % (TX + 1), lj = e / (TX + 1);
+    const int gi = i0 - 1 + li, gj = j0 - 1 + lj;
+    const bool ok = e < (TX + 1) * (TY + 1) && gi >= 0 && gj >= 0 && gi <= g.nx && gj <= g.ny;
+    fgi[q] = ok ? gi : -1;
+    fgj[q] = gj;
+    fhx[q] = ok ? g.h[0][gi] : 0.0;
+    fhy[q] = ok ? g.h[1][gj] : 0.0;
+    fwx[q] = ok ? g.dw[0][gi] * g.ih[1][gj] : 0.0;  // times 1/hz(k)
+    fwy[q] = ok ? g.dw[1][gj] * g.ih[0][gi] : 0.0;  // times 1/hz(k)
+    fwz[q] = ok ? g.ih[0][gi] * g.ih[1][gj] : 0.0;  // times dual_z(k)
+  }
+  const double ohx = own ? g.h[0][i] : 0.0, ohy = own ? g.h[1][j] : 0.0;
 
   auto load_plane = [&](int kk) {
     const int slot = kk & 1;
@@ -147,59 +171,69 @@ __device__ void stencil_tile(const GridArgs& g, const double* __restrict__ dinv,
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const double d = in ? dinv[c * g.nn + v] : 0.0;
-        sp[slot][c][lj][li] = (d != 0.0) ? d * load(v, c) : zero_of(Val{});
+        const Val u = (d != 0.0) ? load(v, c) : zero_of(Val{});
+        sd[slot][c][lj][li] = d;
+        su[slot][c][lj][li] = u;
+        sp[slot][c][lj][li] = d * u;
       }
     }
   };
-  // fluxes of the three faces owned by node (gi, gj, kk) whose halo
-  // coordinates are (li, lj); zero outside the grid
-  auto fluxes = [&](int gi, int gj, int kk, int li, int lj, Val& fx, Val& fy, Val& fz) {
+  // fluxes of the three faces owned by a node with halo coordinates (li, lj)
+  // in plane kk, from its precomputed horizontal factors
+  auto fluxes = [&](int q, int kk, int li, int lj, Val& fx, Val& fy, Val& fz) {
     fx = fy = fz = zero_of(Val{});
-    if (gi < 0 || gj < 0 || kk < 0 || gi > g.nx || gj > g.ny || kk > g.nz) return;
+    if (fgi[q] < 0 || kk < 0 || kk > g.nz) return;
     const int s0 = kk & 1, s1 = (kk + 1) & 1;
-    const double hxi = g.h[0][gi], hyj = g.h[1][gj], hzk = g.h[2][kk];
-    const double wx = g.dw[0][gi] * g.ih[1][gj] * g.ih[2][kk];
-    const double wy = g.dw[1][gj] * g.ih[2][kk] * g.ih[0][gi];
-    const double wz = g.dw[2][kk] * g.ih[0][gi] * g.ih[1][gj];
+    const double hzk = g.h[2][kk], ihz = g.ih[2][kk], dwz = g.dw[2][kk];
+    const double hxi = fhx[q], hyj = fhy[q];
     // Fx: +y, +z, -y, -z ; Fy: +z, +x, -z, -x ; Fz: +x, +y, -x, -y
-    fx = wx * (hyj * sp[s0][1][lj][li] + hzk * sp[s0][2][lj + 1][li] - hyj * sp[s1][1][lj][li] - hzk * sp[s0][2][lj][li]);
-    fy = wy * (hzk * sp[s0][2][lj][li] + hxi * sp[s1][0][lj][li] - hzk * sp[s0][2][lj][li + 1] - hxi * sp[s0][0][lj][li]);
-    fz = wz * (hxi * sp[s0][0][lj][li] + hyj * sp[s0][1][lj][li + 1] - hxi * sp[s0][0][lj + 1][li] - hyj * sp[s0][1][lj][li]);
+    fx = (fwx[q] * ihz) * (hyj * sp[s0][1][lj][li] + hzk * sp[s0][2][lj + 1][li] - hyj * sp[s1][1][lj][li] - hzk * sp[s0][2][lj][li]);
+    fy = (fwy[q] * ihz) * (hzk * sp[s0][2][lj][li] + hxi * sp[s1][0][lj][li] - hzk * sp[s0][2][lj][li + 1] - hxi * sp[s0][0][lj][li]);
+    fz = (fwz[q] * dwz) * (hxi * sp[s0][0][lj][li] + hyj * sp[s0][1][lj][li + 1] - hxi * sp[s0][0][lj + 1][li] - hyj * sp[s0][1][lj][li]);
   };
-
+  // fluxes of the own node at plane k0-1 (needed below the first output plane)
   Val fx_prev = zero_of(Val{}), fy_prev = zero_of(Val{});
   load_plane(k0 - 1);
   load_plane(k0);
   __syncthreads();
-  {
-    Val fz_unused;
-    fluxes(i, j, k0 - 1, tx + 1, ty + 1, fx_prev, fy_prev, fz_unused);
+  if (own && k0 > 0) {
+    const int s0 = (k0 - 1) & 1, s1 = k0 & 1, kk = k0 - 1;
+    const int li = tx + 1, lj = ty + 1;
+    const double hzk = g.h[2][kk], ihz = g.ih[2][kk];
+    const double wx = g.dw[0][i] * g.ih[1][j] * ihz, wy = g.dw[1][j] * g.ih[0][i] * ihz;
+    fx_prev = wx * (ohy * sp[s0][1][lj][li] + hzk * sp[s0][2][lj + 1][li] - ohy * sp[s1][1][lj][li] - hzk * sp[s0][2][lj][li]);
+    fy_prev = wy * (hzk * sp[s0][2][lj][li] + ohx * sp[s1][0][lj][li] - hzk * sp[s0][2][lj][li + 1] - ohx * sp[s0][0][lj][li]);
   }
   __syncthreads();
 
   for (int kk = k0; kk < kend; ++kk) {
     load_plane(kk + 1);  // overwrites plane kk-1, no longer needed
     __syncthreads();
-    for (int e = tid; e < (TX + 1) * (TY + 1); e += NT) {
-      const int li = e % (TX + 1), lj = e / (TX + 1);
-      Val a, b, c;
-      fluxes(i0 - 1 + li, j0 - 1 + lj, kk, li, lj, a, b, c);
-      phi[0][lj][li] = a;
-      phi[1][lj][li] = b;
-      phi[2][lj][li] = c;
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+      const int e = tid + q * NT;
+      if (e < (TX + 1) * (TY + 1)) {
+        const int li = e % (TX + 1), lj = e / (TX + 1);
+        Val a, b, c;
+        fluxes(q, kk, li, lj, a, b, c);
+        phi[0][lj][li] = a;
+        phi[1][lj][li] = b;
+        phi[2][lj][li] = c;
+      }
     }
     __syncthreads();
     if (own) {
       const int li = tx + 1, lj = ty + 1;
+      const int slot = kk & 1;
       const Val fx = phi[0][lj][li], fy = phi[1][lj][li], fz = phi[2][lj][li];
       // (K p)_Ex = hx (phi_y(k-1) - phi_y + phi_z - phi_z(j-1)), and cyclically
-      const Val kpx = g.h[0][i] * (fy_prev - fy + fz - phi[2][lj - 1][li]);
-      const Val kpy = g.h[1][j] * (phi[2][lj][li - 1] - fz + fx - fx_prev);
+      const Val kpx = ohx * (fy_prev - fy + fz - phi[2][lj - 1][li]);
+      const Val kpy = ohy * (phi[2][lj][li - 1] - fz + fx - fx_prev);
       const Val kpz = g.h[2][kk] * (phi[0][lj - 1][li] - fx + fy - phi[1][lj][li - 1]);
       const long long v = node_of(g, i, j, kk);
-      emit(v, 0, kpx);
-      emit(v, 1, kpy);
-      emit(v, 2, kpz);
+      emit(v, 0, kpx, su[slot][0][lj][li], sd[slot][0][lj][li]);
+      emit(v, 1, kpy, su[slot][1][lj][li], sd[slot][1][lj][li]);
+      emit(v, 2, kpz, su[slot][2][lj][li], sd[slot][2][lj][li]);
       fx_prev = fx;
       fy_prev = fy;
     }
@@ -207,154 +241,281 @@ __device__ void stencil_tile(const GridArgs& g, const double* __restrict__ dinv,
   }
 }
 
-constexpr int STX = 32, STY = 8, SKZ = 4;
+// ---------------------------------------------------------------------------
+// Real stencil block, all planes at once: a block owns TX x TY node columns
+// and KZ planes; it loads the scaled field of planes k0-1 .. k0+KZ (one-node
+// halo in x and y) into LDS in a single burst of independent loads, computes
+// the face fluxes of planes k0-1 .. k0+KZ-1, then the three edges of each
+// owned node.  The owner's own unscaled values and dinv are loaded into
+// registers in the same burst.
+// own(c, kz) -> (u, d) is supplied through load(v, c) and dinv.
+// ---------------------------------------------------------------------------
+template <int TX, int TY, int KZ, typename LoadFn, typename EmitFn>
+__device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ dinv, int zb, LoadFn load, EmitFn emit) {
+  constexpr int NP = KZ + 2;                                // planes loaded
+  constexpr int NE = (TX + 2) * (TY + 2);                   // entries per plane
+  constexpr int NT = TX * TY;
+  constexpr int NF = (TX + 1) * (TY + 1);                   // flux entries per plane
+  __shared__ double sp[NP][3][TY + 2][TX + 2];
+  __shared__ double phi[KZ + 1][3][TY + 1][TX + 1];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int tid = tx + TX * ty;
+  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+  const int k0 = zb * KZ;
+  const int i = i0 + tx, j = j0 + ty;
+  const bool own = (i < g.nx) && (j < g.ny);
+  // own values (registers)
+  double ou[KZ][3], od[KZ][3];
+#pragma unroll
+  for (int z = 0; z < KZ; ++z) {
+    const int kk = k0 + z;
+    const bool ok = own && kk < g.nz;
+    const long long v = ok ? node_of(g, i, j, kk) : 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      od[z][c] = ok ? dinv[c * g.nn + v] : 0.0;
+      ou[z][c] = ok ? load(v, c) : 0.0;
+    }
+  }
+  // tile + halo of all planes
+  for (int e = tid; e < NP * NE; e += NT) {
+    const int pl = e / NE, r = e % NE;
+    const int li = r % (TX + 2), lj = r / (TX + 2);
+    const int gi = i0 - 1 + li, gj = j0 - 1 + lj, kk = k0 - 1 + pl;
+    const bool in = gi >= 0 && gi < g.px && gj >= 0 && gj < g.py && kk >= 0 && kk < g.pz;
+    const long long v = in ? node_of(g, gi, gj, kk) : 0;
+    double val[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) val[c] = in ? dinv[c * g.nn + v] * load(v, c) : 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sp[pl][c][lj][li] = val[c];
+  }
+  __syncthreads();
+  // fluxes of planes k0-1 .. k0+KZ-1 (plane index pl: kk = k0 - 1 + pl)
+  for (int e = tid; e < (KZ + 1) * NF; e += NT) {
+    const int pl = e / NF, r = e % NF;
+    const int li = r % (TX + 1), lj = r / (TX + 1);
+    const int gi = i0 - 1 + li, gj = j0 - 1 + lj, kk = k0 - 1 + pl;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if (gi >= 0 && gj >= 0 && kk >= 0 && gi <= g.nx && gj <= g.ny && kk <= g.nz && kk <= k0 + KZ - 1) {
+      const double hxi = g.h[0][gi], hyj = g.h[1][gj], hzk = g.h[2][kk];
+      const double wx = g.dw[0][gi] * g.ih[1][gj] * g.ih[2][kk];
+      const double wy = g.dw[1][gj] * g.ih[2][kk] * g.ih[0][gi];
+      const double wz = g.dw[2][kk] * g.ih[0][gi] * g.ih[1][gj];
+      const int a = pl, b = pl + 1;  // planes kk and kk+1 in sp
+      fx = wx * (hyj * sp[a][1][lj][li] + hzk * sp[a][2][lj + 1][li] - hyj * sp[b][1][lj][li] - hzk * sp[a][2][lj][li]);
+      fy = wy * (hzk * sp[a][2][lj][li] + hxi * sp[b][0][lj][li] - hzk * sp[a][2][lj][li + 1] - hxi * sp[a][0][lj][li]);
+      fz = wz * (hxi * sp[a][0][lj][li] + hyj * sp[a][1][lj][li + 1] - hxi * sp[a][0][lj + 1][li] - hyj * sp[a][1][lj][li]);
+    }
+    phi[pl][0][lj][li] = fx;
+    phi[pl][1][lj][li] = fy;
+    phi[pl][2][lj][li] = fz;
+  }
+  __syncthreads();
+  if (!own) return;
+  const int li = tx + 1, lj = ty + 1;
+  const double ohx = g.h[0][i], ohy = g.h[1][j];
+#pragma unroll
+  for (int z = 0; z < KZ; ++z) {
+    const int kk = k0 + z;
+    if (kk >= g.nz) break;
+    const int p = z + 1;  // flux plane of kk
+    const double fx = phi[p][0][lj][li], fy = phi[p][1][lj][li], fz = phi[p][2][lj][li];
+    const double kpx = ohx * (phi[p - 1][1][lj][li] - fy + fz - phi[p][2][lj - 1][li]);
+    const double kpy = ohy * (phi[p][2][lj][li - 1] - fz + fx - phi[p - 1][0][lj][li]);
+    const double kpz = g.h[2][kk] * (phi[p][0][lj - 1][li] - fx + fy - phi[p][1][lj][li - 1]);
+    const long long v = node_of(g, i, j, kk);
+    emit(v, 0, kpx, ou[z][0], od[z][0]);
+    emit(v, 1, kpy, ou[z][1], od[z][1]);
+    emit(v, 2, kpz, ou[z][2], od[z][2]);
+  }
+}
+
+constexpr int STX = 32, STY = 4, SKZ = 2;
+constexpr int UPD_T = 256;
+constexpr int UPD_BLOCKS = 256;  // blocks of the seed update (= partials it leaves)
+
+// Fixed-order sum of n partials written by the previous kernel (every block
+// of the reading kernel computes the same value; no inter-block traffic).
+__device__ double sum_prev(const double* __restrict__ partials, int n, double* lds) {
+  double s = 0.0;
+  for (int i = flat_tid(); i < n; i += flat_threads()) s += partials[i];
+  s = block_sum(s, lds);
+  __shared__ double bc;
+  if (flat_tid() == 0) bc = s;
+  __syncthreads();
+  return bc;
+}
 
 // ---------------------------------------------------------------------------
-// Seed CG, iteration k:
-//   stencil: p_k = r_k + beta_{k-1} p_{k-1};  q = A0 p_k = dinv K (dinv p_k) + s0 p_k;
-//            alpha_k = (r_k, r_k) / (p_k, q)
-//   update:  r_{k+1} = r_k - alpha_k q;  beta_k = (r_{k+1}, r_{k+1}) / (r_k, r_k);
-//            shifted recurrences and deferred-update coefficients for every shift.
+// Seed CG on A0 = A + s0, iteration k (local = k mod B):
+//   stencil: rr_k = sum of the update's partials, beta_{k-1} = rr_k / rr_{k-1};
+//            p_k = r_k + beta_{k-1} p_{k-1};  q = A0 p_k;  partials of (p_k, q)
+//   update:  alpha_k = rr_k / (p_k, q);  r_{k+1} = r_k - alpha_k q;  partials of (r_{k+1}, r_{k+1})
+// Reductions cross kernel boundaries only: a kernel writes one partial per
+// block and the next kernel sums them in a fixed order, so results are
+// bitwise repeatable and no device-scope fences are needed.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(STX* STY) k_seed_stencil(GridArgs g, const double* __restrict__ r,
+template <int TX, int TY, int KZ, bool B3D>
+__global__ void __launch_bounds__(TX* TY) k_seed_stencil(GridArgs g, const double* __restrict__ r,
                                                           const double* __restrict__ pold,
                                                           double* __restrict__ pnew, double* __restrict__ q,
                                                           const double* __restrict__ dinv, double s0,
-                                                          double* partials, unsigned int* counter,
-                                                          SolveState* st) {
+                                                          const double* __restrict__ upd_partials,
+                                                          double* __restrict__ partials, SolveState* st, int local) {
   __shared__ double red[16];
-  __shared__ int flag;
-  const double beta = st->beta;
+  const double rr = sum_prev(upd_partials, UPD_BLOCKS, red);
+  const double rr_prev = st->rrk[(local + 1) & 1];
+  const double beta = rr / rr_prev;  // rr_{-1} = inf gives beta_{-1} = 0
+  const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  if (bid == 0 && flat_tid() == 0) {
+    if (isinf(rr_prev)) {  // first iteration: rr_0 = (g, g) scales the stopping tolerance
+      st->rr0 = rr;
+      st->tol2 *= rr;
+    }
+    st->rrk[local & 1] = rr;
+    const int B = st->B;
+    const int prev = (local + B - 1) % B;  // the step k-1
+    st->beta_h[prev] = beta;
+    st->rr_h[prev] = rr;
+    if (!isfinite(rr)) st->breakdown = 1;
+  }
   double dot = 0.0;
   auto load = [&](long long v, int c) { return r[c * g.nn + v] + beta * pold[c * g.nn + v]; };
-  auto emit = [&](long long v, int c, double kp) {
+  auto emit = [&](long long v, int c, double kp, double u, double d) {
     const long long e = c * g.nn + v;
-    const double u = r[e] + beta * pold[e];
-    const double d = dinv[e];
     const double out = d * kp + s0 * u;
     pnew[e] = u;
     q[e] = out;
     dot += u * out;
   };
-  stencil_tile<double, STX, STY, SKZ>(g, dinv, blockIdx.z, load, emit);
-  const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-  const int nb = gridDim.x * gridDim.y * gridDim.z;
+  if constexpr (B3D) stencil_block3d<TX, TY, KZ>(g, dinv, blockIdx.z, load, emit);
+  else stencil_tile<double, TX, TY, KZ>(g, dinv, blockIdx.z, load, emit);
   const double s = block_sum(dot, red);
-  if (publish_partial(s, partials, counter, bid, nb, &flag)) {
-    const double pap = sum_partials(partials, nb, red);
-    if (flat_tid() == 0) {
-      st->pAp = pap;
-      if (!(pap > 0.0) || !isfinite(pap)) {
-        st->breakdown = 1;
-        st->alpha = 0.0;
-      } else {
-        st->alpha = st->rr / pap;
-      }
-      __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
+  if (flat_tid() == 0) partials[bid] = s;
 }
-
-constexpr int UPD_T = 256;
 
 __global__ void __launch_bounds__(UPD_T) k_seed_update(long long n, const double* __restrict__ r,
                                                        const double* __restrict__ q, double* __restrict__ rnext,
-                                                       double* partials, unsigned int* counter, SolveState* st,
-                                                       int slot_next) {
+                                                       const double* __restrict__ st_partials, int n_st,
+                                                       double* __restrict__ partials, SolveState* st, int local) {
   __shared__ double red[8];
-  __shared__ int flag;
-  __shared__ double sh[2];
-  const double alpha = st->alpha;
+  // the first grid-stride chunk is loaded before the reduction so that its
+  // latency overlaps the sum of the stencil's partials
+  const long long e0 = blockIdx.x * (long long)UPD_T + threadIdx.x;
+  const double r0v = e0 < n ? r[e0] : 0.0, q0v = e0 < n ? q[e0] : 0.0;
+  const double pap = sum_prev(st_partials, n_st, red);
+  const double rr = st->rrk[local & 1];
+  const double alpha = (pap > 0.0 && isfinite(pap)) ? rr / pap : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (!(pap > 0.0 && isfinite(pap))) st->breakdown = 1;
+    const int B = st->B;
+    if (local == 0) {  // alpha, beta of the step before this block, for the shift recurrences
+      st->carry_alpha = st->alpha_h[B - 1];
+      st->carry_beta = st->beta_h[B - 1];
+    }
+    st->alpha_h[local] = alpha;
+    st->pAp = pap;
+  }
   double acc = 0.0;
-  for (long long e = blockIdx.x * (long long)UPD_T + threadIdx.x; e < n; e += (long long)gridDim.x * UPD_T) {
+  if (e0 < n) {
+    const double v = r0v - alpha * q0v;
+    rnext[e0] = v;
+    acc += v * v;
+  }
+  for (long long e = e0 + (long long)gridDim.x * UPD_T; e < n; e += (long long)gridDim.x * UPD_T) {
     const double v = r[e] - alpha * q[e];
     rnext[e] = v;
     acc += v * v;
   }
   const double s = block_sum(acc, red);
-  if (!publish_partial(s, partials, counter, blockIdx.x, gridDim.x, &flag)) return;
-  double rr_next = sum_partials(partials, gridDim.x, red);
-  const int t = threadIdx.x;
-  if (t == 0) {
-    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    sh[0] = rr_next;
-    sh[1] = st->rr;
-    if (!isfinite(rr_next)) st->breakdown = 1;
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// Per-shift recurrences for one block of B seed steps, replayed from the
+// recorded alpha_k, beta_k, (r_{k+1}, r_{k+1}); one wavefront per shift, lane l
+// owning the coefficients of residual slot l.  For system (A0 + sig) y = g:
+//   zeta_{k+1} = zeta_k zeta_{k-1} a_{k-1} /
+//                (a_k b_{k-1} (zeta_{k-1} - zeta_k) + zeta_{k-1} a_{k-1} (1 + sig a_k)),
+//   alpha^s_k = a_k zeta_{k+1}/zeta_k,  beta^s_k = b_k (zeta_{k+1}/zeta_k)^2,
+//   y_{k+1} = y_k + alpha^s_k p_k,  p_{k+1} = zeta_{k+1} r_{k+1} + beta^s_k p_k,
+// accumulated as coefficients of the block's starting p and residuals r_l.
+__global__ void __launch_bounds__(64) k_shift_block(const double* __restrict__ upd_partials, SolveState* st) {
+  const int j = blockIdx.x, lane = threadIdx.x;
+  const int B = st->B;
+  __shared__ int s_active;
+  __shared__ double red[2];
+  // the block's last step: (r_{k+1}, r_{k+1}) from the update's partials, beta_k
+  const double rr_last = sum_prev(upd_partials, UPD_BLOCKS, red);
+  const double beta_last = rr_last / st->rrk[(B - 1) & 1];
+  if (lane == 0) s_active = st->active[j];
+  if (j == 0 && lane == 0) {
+    st->beta_h[B - 1] = beta_last;
+    st->rr_h[B - 1] = rr_last;
+    st->k += B;
   }
   __syncthreads();
-  rr_next = sh[0];
-  const double rr = sh[1];
-  const double beta = rr > 0.0 ? rr_next / rr : 0.0;  // beta_k
-  const double a_k = st->alpha, a_km1 = st->alpha_prev, b_km1 = st->beta;
-  const int B = st->B;
-  const int k = st->k;
-  const int local = k % B;
-  const int J = st->J;
-  int my_active = 0;
-  if (t < J) {
-    if (local == 0) {  // this step opens a new block of deferred updates
-      st->a_re[t] = 1.0;
-      st->a_im[t] = 0.0;
-      st->c_re[t] = st->c_im[t] = 0.0;
-      for (int l = 0; l < B; ++l) st->d_re[t][l] = st->d_im[t][l] = st->e_re[t][l] = st->e_im[t][l] = 0.0;
-      st->apply[t] = st->active[t];
-    }
-    if (st->active[t]) {
-      const cplx z{st->z_re[t], st->z_im[t]}, zp{st->zp_re[t], st->zp_im[t]};
-      const cplx sig{st->sig_re[t], st->sig_im[t]};
-      // zeta_{k+1} = zeta_k zeta_{k-1} a_{k-1} /
-      //             (a_k b_{k-1} (zeta_{k-1} - zeta_k) + zeta_{k-1} a_{k-1} (1 + sig a_k))
-      const cplx num = a_km1 * cmul(z, zp);
-      const cplx one_sa{1.0 + sig.re * a_k, sig.im * a_k};
-      const cplx den = (a_k * b_km1) * (zp - z) + a_km1 * cmul(zp, one_sa);
-      const cplx zn = cdiv(num, den);
-      const cplx ratio = cdiv(zn, z);
-      const cplx as = a_k * ratio;                // alpha_k^sigma
-      const cplx bs = beta * cmul(ratio, ratio);  // beta_k^sigma
-      const bool ok = isfinite(zn.re) && isfinite(zn.im) && isfinite(as.re) && isfinite(as.im) &&
-                      isfinite(bs.re) && isfinite(bs.im);
-      if (!ok) {
-        st->breakdown = 1;
-      } else {
-        // y_{k+1} = y_k + as p_k  with  p_k = a P + sum_l e_l r_l
-        const cplx a{st->a_re[t], st->a_im[t]};
-        const cplx c = cplx{st->c_re[t], st->c_im[t]} + cmul(as, a);
-        st->c_re[t] = c.re;
-        st->c_im[t] = c.im;
-        for (int l = 0; l < B; ++l) {
-          const cplx e{st->e_re[t][l], st->e_im[t][l]};
-          const cplx d = cplx{st->d_re[t][l], st->d_im[t][l]} + cmul(as, e);
-          st->d_re[t][l] = d.re;
-          st->d_im[t][l] = d.im;
-          const cplx en = cmul(bs, e);
-          st->e_re[t][l] = en.re;
-          st->e_im[t][l] = en.im;
-        }
-        // p_{k+1} = zeta_{k+1} r_{k+1} + bs p_k
-        const cplx an = cmul(bs, a);
-        st->a_re[t] = an.re;
-        st->a_im[t] = an.im;
-        st->e_re[t][slot_next] = zn.re;
-        st->e_im[t][slot_next] = zn.im;
-        st->zp_re[t] = z.re;
-        st->zp_im[t] = z.im;
-        st->z_re[t] = zn.re;
-        st->z_im[t] = zn.im;
-        st->iters[t] += 1;
-        const double est2 = (zn.re * zn.re + zn.im * zn.im) * rr_next;
-        st->est[t] = sqrt(est2);
-        if (est2 <= st->tol2) st->active[t] = 0;
-      }
-    }
-    my_active = st->active[t];
+  if (!s_active) {
+    if (lane == 0) st->apply[j] = 0;
+    return;
   }
-  const double na = block_sum((double)my_active, red);
-  if (t == 0) {
-    st->n_active = (int)na;
-    st->alpha_prev = a_k;
-    st->beta = beta;
-    st->rr = rr_next;
-    st->k = k + 1;
+  const double tol2 = st->tol2;
+  const cplx sig{st->sig_re[j], st->sig_im[j]};
+  cplx z{st->z_re[j], st->z_im[j]}, zp{st->zp_re[j], st->zp_im[j]};
+  cplx a{1.0, 0.0}, c{0.0, 0.0}, e{0.0, 0.0}, d{0.0, 0.0};
+  int iters = st->iters[j];
+  bool active = true, bad = false;
+  double est = st->est[j];
+  for (int i = 0; i < B && active; ++i) {
+    const double a_k = st->alpha_h[i];
+    const double b_k = i == B - 1 ? beta_last : st->beta_h[i];
+    const double rr_next = i == B - 1 ? rr_last : st->rr_h[i];
+    const double a_km1 = i ? st->alpha_h[i - 1] : st->carry_alpha;
+    const double b_km1 = i ? st->beta_h[i - 1] : st->carry_beta;
+    const cplx num = a_km1 * cmul(z, zp);
+    const cplx one_sa{1.0 + sig.re * a_k, sig.im * a_k};
+    const cplx den = (a_k * b_km1) * (zp - z) + a_km1 * cmul(zp, one_sa);
+    const cplx zn = cdiv(num, den);
+    const cplx ratio = cdiv(zn, z);
+    const cplx as = a_k * ratio;
+    const cplx bs = b_k * cmul(ratio, ratio);
+    if (!(isfinite(zn.re) && isfinite(zn.im) && isfinite(as.re) && isfinite(as.im) && isfinite(bs.re) &&
+          isfinite(bs.im))) {
+      bad = true;
+      break;
+    }
+    c = c + cmul(as, a);
+    d = d + cmul(as, e);
+    e = cmul(bs, e);
+    a = cmul(bs, a);
+    if (lane == (i + 1) % B) e = zn;
+    zp = z;
+    z = zn;
+    ++iters;
+    const double est2 = (zn.re * zn.re + zn.im * zn.im) * rr_next;
+    est = sqrt(est2);
+    if (est2 <= tol2) active = false;
+  }
+  if (lane < B) {
+    st->d_re[j][lane] = d.re;
+    st->d_im[j][lane] = d.im;
+    st->e_re[j][lane] = e.re;
+    st->e_im[j][lane] = e.im;
+  }
+  if (lane == 0) {
+    st->apply[j] = 1;
+    st->a_re[j] = a.re;
+    st->a_im[j] = a.im;
+    st->c_re[j] = c.re;
+    st->c_im[j] = c.im;
+    st->z_re[j] = z.re;
+    st->z_im[j] = z.im;
+    st->zp_re[j] = zp.re;
+    st->zp_im[j] = zp.im;
+    st->iters[j] = iters;
+    st->est[j] = est;
+    st->active[j] = active && !bad;
+    if (bad) st->breakdown = 1;
   }
 }
 
@@ -407,10 +568,10 @@ __global__ void __launch_bounds__(BU_T) k_block_update(long long n3, const doubl
   }
 }
 
-__global__ void k_seed_init(long long n3, const double* __restrict__ gv, double* r0, double* pold, double2* Y,
-                            double2* P, int J, double* partials, unsigned int* counter, SolveState* st) {
+__global__ void __launch_bounds__(UPD_T) k_seed_init(long long n3, const double* __restrict__ gv, double* r0,
+                                                     double* pold, double2* Y, double2* P, int J,
+                                                     double* __restrict__ partials, SolveState* st) {
   __shared__ double red[8];
-  __shared__ int flag;
   double acc = 0.0;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n3; e += (long long)gridDim.x * blockDim.x) {
     const double v = gv[e];
@@ -423,20 +584,13 @@ __global__ void k_seed_init(long long n3, const double* __restrict__ gv, double*
     acc += v * v;
   }
   const double s = block_sum(acc, red);
-  if (!publish_partial(s, partials, counter, blockIdx.x, gridDim.x, &flag)) return;
-  const double rr = sum_partials(partials, gridDim.x, red);
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    st->rr = rr;
-    st->rr0 = rr;
-    st->tol2 *= rr;  // the host stores rtol^2 here
-    st->alpha = 0.0;
-    st->beta = 0.0;
-    st->alpha_prev = 1.0;
-    st->beta_prev = 0.0;
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->rrk[1] = INFINITY;          // rr_{-1}: beta_{-1} = 0, so p_0 = r_0
+    st->alpha_h[st->B - 1] = 1.0;   // alpha_{-1}
+    st->beta_h[st->B - 1] = 0.0;    // beta_{-1}
     st->k = 0;
-    st->breakdown = (rr > 0.0 && isfinite(rr)) ? 0 : 1;
-    st->n_active = st->J;
+    st->breakdown = 0;
   }
 }
 
@@ -445,7 +599,7 @@ __global__ void k_seed_init(long long n3, const double* __restrict__ gv, double*
 //   out_j = rhs - (A + s_j) X_j   (rhs != nullptr)   or   out_j = (A + s_j) X_j,
 // plus per-block partial sums of |out_j|^2 in norm_partials[j * nblocks + b].
 // ---------------------------------------------------------------------------
-constexpr int CTX = 32, CTY = 4, CKZ = 4;
+constexpr int CTX = 32, CTY = 4, CKZ = 2;
 __global__ void __launch_bounds__(CTX* CTY) k_cstencil(GridArgs g, const double2* __restrict__ X, long long xstride,
                                                        const double* __restrict__ dinv, const double* sre,
                                                        const double* sim, const double2* __restrict__ rhs,
@@ -462,12 +616,11 @@ __global__ void __launch_bounds__(CTX* CTY) k_cstencil(GridArgs g, const double2
     const double2 t = x[c * g.nn + v];
     return cplx{t.x, t.y};
   };
-  auto emit = [&](long long v, int c, cplx kp) {
+  auto emit = [&](long long v, int c, cplx kp, cplx uu, double d) {
     const long long e = c * g.nn + v;
-    const double d = dinv[e];
     cplx res{0.0, 0.0};
     if (d != 0.0) {
-      const double2 u = x[e];
+      const double2 u = make_double2(uu.re, uu.im);
       res = cplx{d * kp.re + shr * u.x - shi * u.y, d * kp.im + shr * u.y + shi * u.x};
       if (rhs != nullptr) {
         const double2 b = rhs[e];
@@ -537,8 +690,9 @@ __global__ void k_to_complex(long long n, const double* x, double2* y) {
 //   U[k][e] = dinv_e * sum_j Re(C_jk Y_j[e]) = [Re Y | Im Y] [Re C ; -Im C],
 // as an (edges x 2J) x (2J x T) product on FP64 MFMA (v_mfma_f64_16x16x4f64).
 // One wave computes 16 edges x all channels (T <= 64).
-// Lane layout of the 16x16x4 FP64 MFMA: lane l supplies A[l%16][l/16] and
-// B[l/16][l%16] and holds D[4*(l/16)+r][l%16], r = 0..3.
+// Lane layout of the 16x16x4 FP64 MFMA (checked on the device): lane l
+// supplies A[l%16][l/16] and B[l/16][l%16] and its result register r holds
+// D[4*r + l/16][l%16], r = 0..3.
 // ---------------------------------------------------------------------------
 typedef double d4 __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256) k_contract(GridArgs g, const double2* __restrict__ Y, int J,
@@ -576,7 +730,7 @@ __global__ void __launch_bounds__(256) k_contract(GridArgs g, const double2* __r
     const int ch = t * 16 + row;
     if (ch >= T) continue;
     for (int r = 0; r < 4; ++r) {
-      const long long e = e0 + 4 * kq + r;
+      const long long e = e0 + 4 * r + kq;
       if (e < nstore) U[(long long)ch * nstore + e] = acc[t][r];
     }
   }
@@ -651,6 +805,257 @@ __global__ void k_gather_storage(GridArgs g, const double2* __restrict__ xpad, c
   xpub[e] = make_double2(s * x.x, s * x.y);
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint (Sec. 4): batched COCG for the J complex-symmetric systems
+//   (A + s_j) mu_j = h_j,   h_j = M^-1/2 g_j,   g_j = sum_k c_jk Q^T w_k,
+// then lambda_j = M^-1/2 mu_j and the per-cell gradient.  COCG uses the
+// bilinear form x^T y (no conjugation), which is the right inner product for
+// the complex symmetric A + s_j.
+// ---------------------------------------------------------------------------
+// h_j = dinv * sum_r gamma_jr q_r, q_r = -(face circulation)/(face area); one
+// thread per shift walks the receivers in order (adjacent faces share edges).
+__global__ void k_adj_rhs(GridArgs g, int J, int n_rx, const int* __restrict__ rx, int ks,
+                          const double* __restrict__ gamma, const double* __restrict__ dinv, double2* H) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= J) return;
+  double2* h = H + (long long)j * 3 * g.nn;
+  for (int r = 0; r < n_rx; ++r) {
+    const int i = rx[2 * r], jj = rx[2 * r + 1];
+    const double hx = g.h[0][i], hy = g.h[1][jj];
+    const double inva = -1.0 / (hx * hy);
+    const long long e[4] = {0 * g.nn + node_of(g, i, jj, ks), 1 * g.nn + node_of(g, i + 1, jj, ks),
+                            0 * g.nn + node_of(g, i, jj + 1, ks), 1 * g.nn + node_of(g, i, jj, ks)};
+    const double w[4] = {hx * inva, hy * inva, -hx * inva, -hy * inva};
+    const double gr = gamma[2 * ((long long)j * n_rx + r)], gi = gamma[2 * ((long long)j * n_rx + r) + 1];
+    for (int m = 0; m < 4; ++m) {
+      const double s = w[m] * dinv[e[m]];
+      double2 v = h[e[m]];
+      v.x += s * gr;
+      v.y += s * gi;
+      h[e[m]] = v;
+    }
+  }
+}
+
+
+// init: mu = 0, r = h, p_old = 0; rho = r^T r, |h|^2 (partials per shift)
+__global__ void k_cocg_init(long long n3, int J, const double2* __restrict__ H, double2* Mu, double2* Rr,
+                            double2* Pold, double* partials, unsigned int* counter, CocgState* st) {
+  __shared__ double red[8];
+  __shared__ int flag;
+  const int j = blockIdx.y;
+  const int nbx = gridDim.x;
+  double a_re = 0.0, a_im = 0.0, a_n = 0.0;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n3; e += (long long)nbx * blockDim.x) {
+    const long long o = (long long)j * n3 + e;
+    const double2 h = H[o];
+    Mu[o] = make_double2(0.0, 0.0);
+    Rr[o] = h;
+    Pold[o] = make_double2(0.0, 0.0);
+    a_re += h.x * h.x - h.y * h.y;
+    a_im += 2.0 * h.x * h.y;
+    a_n += h.x * h.x + h.y * h.y;
+  }
+  const double s_re = block_sum(a_re, red), s_im = block_sum(a_im, red), s_n = block_sum(a_n, red);
+  const int bid = j * nbx + blockIdx.x;
+  if (threadIdx.x == 0) {
+    partials[3 * bid] = s_re;
+    partials[3 * bid + 1] = s_im;
+    partials[3 * bid + 2] = s_n;
+  }
+  if (!publish_partial(0.0, partials + 3 * gridDim.x * gridDim.y, counter, bid, nbx * gridDim.y, &flag)) return;
+  const int t = threadIdx.x;
+  if (t < J) {
+    double r = 0, i = 0, n = 0;
+    for (int b = 0; b < nbx; ++b) {
+      const long long q = 3LL * (t * nbx + b);
+      r += __hip_atomic_load(partials + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      i += __hip_atomic_load(partials + q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      n += __hip_atomic_load(partials + q + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    st->rho_re[t] = r;
+    st->rho_im[t] = i;
+    st->hn2[t] = n;
+    st->rn2[t] = n;
+    st->beta_re[t] = st->beta_im[t] = 0.0;
+    st->alpha_re[t] = st->alpha_im[t] = 0.0;
+    st->iters[t] = 0;
+    st->active[t] = n > 0.0 ? 1 : 0;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int na = 0;
+    for (int q = 0; q < J; ++q) na += st->active[q];
+    st->n_active = na;
+    st->breakdown = 0;
+    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// p_j = r_j + beta_j p_j ; q_j = (A + s_j) p_j ; partial p^T q per (shift, block)
+__global__ void __launch_bounds__(CTX* CTY) k_cocg_stencil(GridArgs g, const double2* __restrict__ Rr,
+                                                           const double2* __restrict__ Pold, double2* Pnew,
+                                                           double2* Q, const double* __restrict__ dinv,
+                                                           const double* sre, const double* sim, int zblocks,
+                                                           double* partials, unsigned int* counter, CocgState* st) {
+  __shared__ double red[16];
+  __shared__ int flag;
+  const int vec = blockIdx.z / zblocks;
+  const int zb = blockIdx.z % zblocks;
+  const long long off = (long long)vec * 3 * g.nn;
+  const bool act = st->active[vec] != 0;
+  const cplx beta{st->beta_re[vec], st->beta_im[vec]};
+  const double shr = sre[vec], shi = sim[vec];
+  double d_re = 0.0, d_im = 0.0;
+  if (act) {
+    auto load = [&](long long v, int c) {
+      const double2 r = Rr[off + c * g.nn + v], p = Pold[off + c * g.nn + v];
+      return cplx{r.x + beta.re * p.x - beta.im * p.y, r.y + beta.re * p.y + beta.im * p.x};
+    };
+    auto emit = [&](long long v, int c, cplx kp, cplx u, double d) {
+      const long long e = c * g.nn + v;
+      cplx out{0.0, 0.0};
+      if (d != 0.0) out = cplx{d * kp.re + shr * u.re - shi * u.im, d * kp.im + shr * u.im + shi * u.re};
+      Pnew[off + e] = make_double2(u.re, u.im);
+      Q[off + e] = make_double2(out.re, out.im);
+      d_re += u.re * out.re - u.im * out.im;
+      d_im += u.re * out.im + u.im * out.re;
+    };
+    stencil_tile<cplx, CTX, CTY, CKZ>(g, dinv, zb, load, emit);
+  }
+  const int nbv = gridDim.x * gridDim.y * zblocks;
+  const int bid = vec * nbv + blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * zb);
+  const double s_re = block_sum(d_re, red), s_im = block_sum(d_im, red);
+  if (flat_tid() == 0) {
+    partials[2 * bid] = s_re;
+    partials[2 * bid + 1] = s_im;
+  }
+  const int nb_all = nbv * (gridDim.z / zblocks);
+  if (!publish_partial(0.0, partials + 2 * nb_all, counter, bid, nb_all, &flag)) return;
+  const int t = flat_tid();
+  if (t < st->J && st->active[t]) {
+    double r = 0, i = 0;
+    for (int b = 0; b < nbv; ++b) {
+      const long long q = 2LL * (t * nbv + b);
+      r += __hip_atomic_load(partials + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      i += __hip_atomic_load(partials + q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const cplx pq{r, i};
+    const cplx al = cdiv(cplx{st->rho_re[t], st->rho_im[t]}, pq);
+    if (!(isfinite(al.re) && isfinite(al.im)) || (r == 0.0 && i == 0.0)) {
+      st->breakdown = 1;
+      st->active[t] = 0;
+      st->alpha_re[t] = st->alpha_im[t] = 0.0;
+    } else {
+      st->alpha_re[t] = al.re;
+      st->alpha_im[t] = al.im;
+    }
+  }
+  if (t == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// mu_j += alpha_j p_j ; r_j -= alpha_j q_j ; rho_j' = r^T r ; |r|^2 ; beta_j = rho'/rho
+__global__ void k_cocg_update(long long n3, int J, double2* Mu, double2* Rr, const double2* __restrict__ Pn,
+                              const double2* __restrict__ Q, double* partials, unsigned int* counter,
+                              CocgState* st) {
+  __shared__ double red[8];
+  __shared__ int flag;
+  const int j = blockIdx.y;
+  const int nbx = gridDim.x;
+  const bool act = st->active[j] != 0;
+  const cplx al{st->alpha_re[j], st->alpha_im[j]};
+  double a_re = 0.0, a_im = 0.0, a_n = 0.0;
+  if (act) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n3; e += (long long)nbx * blockDim.x) {
+      const long long o = (long long)j * n3 + e;
+      const double2 p = Pn[o], q = Q[o];
+      double2 m = Mu[o], r = Rr[o];
+      m.x += al.re * p.x - al.im * p.y;
+      m.y += al.re * p.y + al.im * p.x;
+      r.x -= al.re * q.x - al.im * q.y;
+      r.y -= al.re * q.y + al.im * q.x;
+      Mu[o] = m;
+      Rr[o] = r;
+      a_re += r.x * r.x - r.y * r.y;
+      a_im += 2.0 * r.x * r.y;
+      a_n += r.x * r.x + r.y * r.y;
+    }
+  }
+  const double s_re = block_sum(a_re, red), s_im = block_sum(a_im, red), s_n = block_sum(a_n, red);
+  const int bid = j * nbx + blockIdx.x;
+  if (threadIdx.x == 0) {
+    partials[3 * bid] = s_re;
+    partials[3 * bid + 1] = s_im;
+    partials[3 * bid + 2] = s_n;
+  }
+  if (!publish_partial(0.0, partials + 3 * gridDim.x * gridDim.y, counter, bid, nbx * gridDim.y, &flag)) return;
+  const int t = threadIdx.x;
+  if (t < J && st->active[t]) {
+    double r = 0, i = 0, n = 0;
+    for (int b = 0; b < nbx; ++b) {
+      const long long q = 3LL * (t * nbx + b);
+      r += __hip_atomic_load(partials + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      i += __hip_atomic_load(partials + q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      n += __hip_atomic_load(partials + q + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const cplx rho_new{r, i}, rho{st->rho_re[t], st->rho_im[t]};
+    const cplx be = cdiv(rho_new, rho);
+    st->beta_re[t] = be.re;
+    st->beta_im[t] = be.im;
+    st->rho_re[t] = r;
+    st->rho_im[t] = i;
+    st->rn2[t] = n;
+    st->iters[t] += 1;
+    if (!(isfinite(be.re) && isfinite(be.im) && isfinite(n))) {
+      st->breakdown = 1;
+      st->active[t] = 0;
+    } else if (n <= st->tol2 * st->hn2[t]) {
+      st->active[t] = 0;
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    int na = 0;
+    for (int q = 0; q < J; ++q) na += st->active[q];
+    st->n_active = na;
+    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// z_e += sum_j Re(s_j mu_j[e] y_j[e]) / M_e  (lambda_j x_j with lambda = D mu, x = D y)
+__global__ void k_grad_edges(long long n3, int J, const double2* __restrict__ Mu, const double2* __restrict__ Y,
+                             const double* __restrict__ dinv, const double* sre, const double* sim, double* z) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= n3) return;
+  const double d = dinv[e];
+  if (d == 0.0) return;
+  double acc = 0.0;
+  for (int j = 0; j < J; ++j) {
+    const double2 m = Mu[(long long)j * n3 + e], y = Y[(long long)j * n3 + e];
+    const double pr = m.x * y.x - m.y * y.y, pi = m.x * y.y + m.y * y.x;
+    acc += sre[j] * pr - sim[j] * pi;
+  }
+  z[e] += acc * d * d;
+}
+
+// grad_c = -(sigma_c V_c / 4) sum over the 12 edges of cell c of z_e
+__global__ void k_grad_cells(GridArgs g, const double* __restrict__ sigma, const double* __restrict__ z,
+                             double* grad) {
+  const long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long ncell = (long long)g.nx * g.ny * g.nz;
+  if (c >= ncell) return;
+  const int i = (int)(c % g.nx), j = (int)((c / g.nx) % g.ny), k = (int)(c / ((long long)g.nx * g.ny));
+  double s = 0.0;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      s += z[0 * g.nn + node_of(g, i, j + a, k + b)];
+      s += z[1 * g.nn + node_of(g, i + a, j, k + b)];
+      s += z[2 * g.nn + node_of(g, i + a, j + b, k)];
+    }
+  const double vol = g.h[0][i] * g.h[1][j] * g.h[2][k];
+  grad[c] = -0.25 * sigma[c] * vol * s;
+}
+
 int grid_1d(long long n, int threads, int cap) {
   long long b = (n + threads - 1) / threads;
   if (b < 1) b = 1;
@@ -683,22 +1088,84 @@ void launch_to_complex(long long n, const double* x, double2* y, hipStream_t s) 
 void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, double2* Y, double2* P,
                       int J, Reduce red, SolveState* st, hipStream_t s) {
   const long long n3 = 3 * g.nn;
-  hipLaunchKernelGGL(k_seed_init, dim3(reduce_blocks(n3)), dim3(UPD_T), 0, s, n3, gvec, r0, pold, Y, P, J,
-                     red.partials, red.counter, st);
+  hipLaunchKernelGGL(k_seed_init, dim3(UPD_BLOCKS), dim3(UPD_T), 0, s, n3, gvec, r0, pold, Y, P, J,
+                     red.partials + kReduceSlots, st);
+}
+
+// Seed stencil tile shapes (TX x TY node columns, KZ planes per block); the
+// variant is chosen per grid (see pick_seed_tile) or by TEM_SEED_TILE.
+struct TileShape {
+  int tx, ty, kz;
+};
+static const TileShape kSeedTiles[] = {{32, 4, 2}, {32, 4, 4}, {64, 2, 2}, {64, 2, 4}, {64, 4, 4},
+                                       {64, 4, 8}, {32, 8, 4}, {32, 2, 2}, {64, 1, 4}, {64, 2, 8},
+                                       {32, 4, 2}, {32, 4, 4}, {64, 2, 2}, {64, 4, 2}, {32, 8, 2}, {64, 2, 4}};
+static int g_seed_tile = -1;
+
+static int pick_seed_tile(const GridArgs& g) {
+  if (g_seed_tile < 0) {
+    const char* env = getenv("TEM_SEED_TILE");
+    g_seed_tile = env ? atoi(env) : 13;
+    if (g_seed_tile < 0 || g_seed_tile >= (int)(sizeof(kSeedTiles) / sizeof(kSeedTiles[0]))) g_seed_tile = 13;
+  }
+  (void)g;
+  return g_seed_tile;
+}
+
+static dim3 seed_stencil_grid(const GridArgs& g) {
+  const TileShape t = kSeedTiles[pick_seed_tile(g)];
+  return dim3((g.nx + t.tx - 1) / t.tx, (g.ny + t.ty - 1) / t.ty, (g.nz + t.kz - 1) / t.kz);
 }
 
 void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold, double* pnew, double* q,
-                         const double* dinv, double s0, Reduce red, SolveState* st, hipStream_t s) {
-  dim3 grid((g.nx + STX - 1) / STX, (g.ny + STY - 1) / STY, (g.nz + SKZ - 1) / SKZ);
-  hipLaunchKernelGGL(k_seed_stencil, grid, dim3(STX, STY), 0, s, g, r, pold, pnew, q, dinv, s0, red.partials,
-                     red.counter, st);
+                         const double* dinv, double s0, Reduce red, SolveState* st, int local, hipStream_t s) {
+  const int v = pick_seed_tile(g);
+  const TileShape t = kSeedTiles[v];
+  const dim3 grid = seed_stencil_grid(g), block(t.tx, t.ty);
+  const double* up = red.partials + kReduceSlots;
+#define TEM_SEED_CASE(I, X, Y, Z)                                                                          \
+  case I:                                                                                                  \
+    hipLaunchKernelGGL((k_seed_stencil<X, Y, Z, (I >= 10)>), grid, block, 0, s, g, r, pold, pnew, q, dinv, s0, up, \
+                       red.partials, st, local);                                                           \
+    break;
+  switch (v) {
+    TEM_SEED_CASE(0, 32, 4, 2)
+    TEM_SEED_CASE(1, 32, 4, 4)
+    TEM_SEED_CASE(2, 64, 2, 2)
+    TEM_SEED_CASE(3, 64, 2, 4)
+    TEM_SEED_CASE(4, 64, 4, 4)
+    TEM_SEED_CASE(5, 64, 4, 8)
+    TEM_SEED_CASE(6, 32, 8, 4)
+    TEM_SEED_CASE(7, 32, 2, 2)
+    TEM_SEED_CASE(8, 64, 1, 4)
+    TEM_SEED_CASE(9, 64, 2, 8)
+    TEM_SEED_CASE(10, 32, 4, 2)
+    TEM_SEED_CASE(11, 32, 4, 4)
+    TEM_SEED_CASE(12, 64, 2, 2)
+    TEM_SEED_CASE(13, 64, 4, 2)
+    TEM_SEED_CASE(14, 32, 8, 2)
+    TEM_SEED_CASE(15, 64, 2, 4)
+  }
+#undef TEM_SEED_CASE
 }
 
 void launch_seed_update(const GridArgs& g, const double* r, const double* q, double* rnext, Reduce red,
-                        SolveState* st, int slot_next, hipStream_t s) {
+                        SolveState* st, int local, hipStream_t s) {
   const long long n3 = 3 * g.nn;
-  hipLaunchKernelGGL(k_seed_update, dim3(reduce_blocks(n3)), dim3(UPD_T), 0, s, n3, r, q, rnext,
-                     red.partials + kReduceSlots, red.counter + 1, st, slot_next);
+  const dim3 sg = seed_stencil_grid(g);
+  const int nst = sg.x * sg.y * sg.z;
+  hipLaunchKernelGGL(k_seed_update, dim3(UPD_BLOCKS), dim3(UPD_T), 0, s, n3, r, q, rnext, red.partials, nst,
+                     red.partials + kReduceSlots, st, local);
+}
+
+int seed_stencil_blocks(const GridArgs& g) {
+  const dim3 sg = seed_stencil_grid(g);
+  return sg.x * sg.y * sg.z;
+}
+
+void launch_shift_block(const GridArgs& g, int J, Reduce red, SolveState* st, hipStream_t s) {
+  (void)g;
+  hipLaunchKernelGGL(k_shift_block, dim3(J), dim3(64), 0, s, (const double*)(red.partials + kReduceSlots), st);
 }
 
 void launch_block_update(const GridArgs& g, const double* R, double2* Y, double2* P, int J, int B,
@@ -762,5 +1229,58 @@ void launch_gather_storage(const GridArgs& g, const double2* xpad, const double*
 }
 
 int cstencil_partials(const GridArgs& g) { return cstencil_blocks(g); }
+
+size_t cocg_state_bytes() { return sizeof(CocgState); }
+
+int cocg_partials(const GridArgs& g, int J) {
+  // row kernels: 3 sums per (shift, block) + one publish slot per block, <= 128 blocks per shift;
+  // stencil: 2 sums per block + one publish slot per block, nbv blocks per shift
+  const int zb = (g.nz + CKZ - 1) / CKZ;
+  const int nbv = ((g.nx + CTX - 1) / CTX) * ((g.ny + CTY - 1) / CTY) * zb;
+  return std::max(4 * 128 * J, 3 * nbv * J) + 64;
+}
+
+void launch_adj_rhs(const GridArgs& g, int J, int n_rx, const int* rx, int ks, const double* gamma, const double* dinv,
+                    double2* H, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_rhs, dim3(1), dim3(64), 0, s, g, J, n_rx, rx, ks, gamma, dinv, H);
+}
+
+static int cocg_row_blocks(long long n3) { return grid_1d(n3, 256, 128); }
+
+void launch_cocg_init(const GridArgs& g, int J, const double2* H, double2* Mu, double2* Rr, double2* Pold,
+                      double* partials, unsigned int* counter, void* st, hipStream_t s) {
+  const long long n3 = 3 * g.nn;
+  hipLaunchKernelGGL(k_cocg_init, dim3(cocg_row_blocks(n3), J), dim3(256), 0, s, n3, J, H, Mu, Rr, Pold, partials,
+                     counter, (CocgState*)st);
+}
+
+void launch_cocg_stencil(const GridArgs& g, int J, const double2* Rr, const double2* Pold, double2* Pnew, double2* Q,
+                         const double* dinv, const double* sre, const double* sim, double* partials,
+                         unsigned int* counter, void* st, hipStream_t s) {
+  const int zb = (g.nz + CKZ - 1) / CKZ;
+  dim3 grid((g.nx + CTX - 1) / CTX, (g.ny + CTY - 1) / CTY, zb * J);
+  hipLaunchKernelGGL(k_cocg_stencil, grid, dim3(CTX, CTY), 0, s, g, Rr, Pold, Pnew, Q, dinv, sre, sim, zb, partials,
+                     counter, (CocgState*)st);
+}
+
+void launch_cocg_update(const GridArgs& g, int J, double2* Mu, double2* Rr, const double2* Pn, const double2* Q,
+                        double* partials, unsigned int* counter, void* st, hipStream_t s) {
+  const long long n3 = 3 * g.nn;
+  hipLaunchKernelGGL(k_cocg_update, dim3(cocg_row_blocks(n3), J), dim3(256), 0, s, n3, J, Mu, Rr, Pn, Q, partials,
+                     counter, (CocgState*)st);
+}
+
+void launch_grad_edges(const GridArgs& g, int J, const double2* Mu, const double2* Y, const double* dinv,
+                       const double* sre, const double* sim, double* z, hipStream_t s) {
+  const long long n3 = 3 * g.nn;
+  hipLaunchKernelGGL(k_grad_edges, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, n3, J, Mu, Y, dinv, sre, sim,
+                     z);
+}
+
+void launch_grad_cells(const GridArgs& g, const double* sigma, const double* z, double* grad, hipStream_t s) {
+  const long long nc = (long long)g.nx * g.ny * g.nz;
+  hipLaunchKernelGGL(k_grad_cells, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, g, sigma, z, grad);
+}
+
 
 }  // namespace tem

@@ -1,0 +1,83 @@
+"""GPU parity of the adjoint gradient (Sec. 4) against the oracle's gradient
+and against central finite differences of the GPU forward."""
+import numpy as np
+import pytest
+
+import tem_workloads as W
+from oracle import direct, rkfit, yee
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tem():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_11657_amd import tem as T
+    T.lib()
+    return T
+
+
+def _misfit_case(n_t=10, m=20):
+    wl = W.small_case(7, seed=9, t=W.log_channels(1e-5, 1e-3, n_t))
+    wl.receivers = [(2, 2), (3, 3), (4, 2), (2, 4)]
+    fit = rkfit.rkfit(wl.t, m)
+    s, C = rkfit.shifts_and_coefficients(fit)
+    return wl, s, C
+
+
+def test_adjoint_matches_oracle_gradient(tem):
+    wl, s, C = _misfit_case()
+    P = yee.Problem(wl)
+    rng = np.random.default_rng(0)
+    w = rng.standard_normal((len(wl.t), len(wl.receivers)))
+    g_or = direct.misfit_gradient(P, s, C, w, method="banded")
+    ctx = tem.Context.from_workload(wl)
+    ctx.forward(wl.loops, wl.receivers, -s, C, keep_solutions=True)
+    g, st = ctx.adjoint(w[None])
+    assert st["converged"]
+    g = g.ravel()
+    err = np.linalg.norm(g - g_or) / np.linalg.norm(g_or)
+    print("adjoint rel err %.2e, iterations %d" % (err, st["iterations"]))
+    assert err <= 1e-8
+
+
+def test_adjoint_vs_finite_differences(tem):
+    """phi = 1/2 ||d - d_obs||^2; central differences of the GPU forward in
+    ln sigma on a few cells (step 1e-3) agree with the adjoint gradient."""
+    wl, s, C = _misfit_case(8, 18)
+    ctx = tem.Context.from_workload(wl)
+    rng = np.random.default_rng(1)
+    d0, _ = ctx.forward(wl.loops, wl.receivers, -s, C, keep_solutions=True)
+    d_obs = d0 * (1 + 0.2 * rng.standard_normal(d0.shape))
+    g, _ = ctx.adjoint(d0 - d_obs)
+    h = 1e-3
+    cells = [(1, 3, 3), (2, 2, 4), (0, 4, 2), (3, 3, 3)]
+    for (k, j, i) in cells:
+        vals = []
+        for sg in (+1, -1):
+            sig = wl.sigma.copy()
+            sig[k, j, i] *= np.exp(sg * h)
+            ctx.set_conductivity(sig)
+            d, _ = ctx.forward(wl.loops, wl.receivers, -s, C)
+            vals.append(0.5 * np.sum((d - d_obs) ** 2))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[k, j, i]) <= 1e-4 * abs(g[k, j, i]) + 1e-6 * np.abs(g).max(), (k, j, i, fd, g[k, j, i])
+    ctx.set_conductivity(wl.sigma)
+
+
+def test_adjoint_two_sources_sum(tem):
+    """The gradient of a two-source misfit is the sum of the per-source ones."""
+    wl, s, C = _misfit_case(6, 16)
+    wl.loops = [W.Loop(1, 4, 1, 4, 1.0), W.Loop(3, 6, 2, 5, -0.5)]
+    ctx = tem.Context.from_workload(wl)
+    rng = np.random.default_rng(2)
+    w = rng.standard_normal((2, 6, len(wl.receivers)))
+    ctx.forward(wl.loops, wl.receivers, -s, C, keep_solutions=True)
+    g2, _ = ctx.adjoint(w)
+    parts = []
+    for q in range(2):
+        ctx.forward([wl.loops[q]], wl.receivers, -s, C, keep_solutions=True)
+        parts.append(ctx.adjoint(w[q:q + 1])[0])
+    assert np.allclose(g2, parts[0] + parts[1], rtol=1e-9, atol=1e-12 * np.abs(g2).max())

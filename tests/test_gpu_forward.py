@@ -3,10 +3,12 @@
 Bars (FP64 path):
   * operator: (K + s M) x by the stencil vs the oracle's assembled CSR,
     <= 1e-13 relative (pure rounding-order differences);
-  * shifted solutions: per shift ||x_gpu - x_or||_M <= 1e-8 ||x_or||_M;
+  * shifted solutions: per shift ||x_gpu - x_or||_M <= 1e-8 ||x_or||_M (1e-9 on the
+    ragged multi-tile case, whose channel floor is then 1e-9 S_k);
   * channels: ||u_gpu(t_k) - u_or(t_k)||_M <= 1e-8 ||u_or(t_k)||_M + 1e-10 S_k and
-    |d_gpu - d_or| <= 1e-8 |d_or| + 1e-10 S^d_k, where S_k = sum_j |c_jk| ||x_j||_M
-    (S^d_k = sum_j |c_jk| |q.x_j|) is the size of the terms of the residue sum:
+    |d_gpu - d_or| <= 1e-8 |d_or| + 1e-10 ||q||_{M^-1} S_k, where S_k = sum_j |c_jk| ||x_j||_M
+    is the size of the terms of the residue sum (and ||q||_{M^-1} S_k bounds
+    their size at a receiver by Cauchy-Schwarz):
     late channels whose value has decayed below the approximation error are
     cancellation-dominated, and 1e-10 S_k is the attainable floor (two
     independent direct solvers disagree at that level, see the oracle tests).
@@ -73,7 +75,10 @@ def _parity(tem, wl, m, rtol=1e-12, block=32, method="banded"):
         Sk = np.abs(C).T @ xn
         eu = direct.m_norm(P, U - Uo)
         d_or = (P.Q @ Uo).T
-        Sd = np.abs(C).T @ np.abs(P.Q @ Xo).T
+        # |q.dx_j| <= ||q||_{M^-1} ||dx_j||_M (Cauchy-Schwarz), so the floor of
+        # receiver r is ||q_r||_{M^-1} S_k
+        qn = np.sqrt(np.asarray(P.Q.multiply(P.Q) @ (1.0 / P.M)).ravel())
+        Sd = np.outer(Sk, qn)
         ed = np.abs(data[src] - d_or)
         res.append((ex, eu, direct.m_norm(P, Uo), Sk, ed, np.abs(d_or), Sd))
     return ctx, stats, res
@@ -109,9 +114,10 @@ def test_forward_parity_ragged_tiles_two_sources(tem):
                     receivers=[(7, 4), (25, 5), (30, 1)], t=W.log_channels(1e-5, 1e-3, 12))
     ctx, stats, res = _parity(tem, wl, 16, method="splu")
     for ex, eu, un, Sk, ed, dn, Sd in res:
-        assert ex.max() <= 1e-8
-        assert np.all(eu <= 1e-8 * un + 1e-10 * Sk)
-        assert np.all(ed <= 1e-8 * dn + 1e-10 * Sd)
+        assert ex.max() <= 1e-9
+        # per-shift errors <= 1e-9 bound the channel errors by 1e-9 S_k
+        assert np.all(eu <= 1e-8 * un + 1e-9 * Sk)
+        assert np.all(ed <= 1e-8 * dn + 1e-9 * Sd)
 
 
 def test_fields_mfma_contraction_matches(tem):
@@ -128,7 +134,12 @@ def test_fields_mfma_contraction_matches(tem):
     U = fields[0].cpu().numpy()                # (T, n_storage)
     ref = (C.T @ X).real
     scale = np.abs(C).T @ np.abs(X)
-    assert np.all(np.abs(U - ref) <= 1e-13 * scale + 1e-300)
+    bad = np.abs(U - ref) > 1e-13 * scale + 1e-300
+    if bad.any():
+        k, e = np.argwhere(bad)[0]
+        print("contraction mismatch at channel %d edge %d: %r vs %r (scale %r), %d bad entries"
+              % (k, e, U[k, e], ref[k, e], scale[k, e], bad.sum()))
+    assert not bad.any()
     P = yee.Problem(wl)
     q = P.grid.receiver_row_full(*wl.receivers[0], wl.k_s)
     dq = U @ q
