@@ -258,6 +258,10 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
   constexpr int NF = (TX + 1) * (TY + 1);                   // flux entries per plane
   __shared__ double sp[NP][3][TY + 2][TX + 2];
   __shared__ double phi[KZ + 1][3][TY + 1][TX + 1];
+  // 1-D weights of the block's flux nodes: x (li = 0..TX), y (lj = 0..TY), z (pl = 0..KZ)
+  __shared__ double wxh[TX + 1], wxi[TX + 1], wxd[TX + 1];
+  __shared__ double wyh[TY + 1], wyi[TY + 1], wyd[TY + 1];
+  __shared__ double wzh[KZ + 1], wzi[KZ + 1], wzd[KZ + 1];
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = tx + TX * ty;
   const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
@@ -275,6 +279,27 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
     for (int c = 0; c < 3; ++c) {
       od[z][c] = ok ? dinv[c * g.nn + v] : 0.0;
       ou[z][c] = ok ? load(v, c) : 0.0;
+    }
+  }
+  for (int e = tid; e < (TX + 1) + (TY + 1) + (KZ + 1); e += NT) {
+    if (e < TX + 1) {
+      const int gi = i0 - 1 + e;
+      const bool ok = gi >= 0 && gi <= g.nx;
+      wxh[e] = ok ? g.h[0][gi] : 0.0;
+      wxi[e] = ok ? g.ih[0][gi] : 0.0;
+      wxd[e] = ok ? g.dw[0][gi] : 0.0;
+    } else if (e < (TX + 1) + (TY + 1)) {
+      const int q = e - (TX + 1), gj = j0 - 1 + q;
+      const bool ok = gj >= 0 && gj <= g.ny;
+      wyh[q] = ok ? g.h[1][gj] : 0.0;
+      wyi[q] = ok ? g.ih[1][gj] : 0.0;
+      wyd[q] = ok ? g.dw[1][gj] : 0.0;
+    } else {
+      const int q = e - (TX + 1) - (TY + 1), kk = k0 - 1 + q;
+      const bool ok = kk >= 0 && kk <= g.nz;
+      wzh[q] = ok ? g.h[2][kk] : 0.0;
+      wzi[q] = ok ? g.ih[2][kk] : 0.0;
+      wzd[q] = ok ? g.dw[2][kk] : 0.0;
     }
   }
   // tile + halo of all planes
@@ -297,11 +322,11 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
     const int li = r % (TX + 1), lj = r / (TX + 1);
     const int gi = i0 - 1 + li, gj = j0 - 1 + lj, kk = k0 - 1 + pl;
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    if (gi >= 0 && gj >= 0 && kk >= 0 && gi <= g.nx && gj <= g.ny && kk <= g.nz && kk <= k0 + KZ - 1) {
-      const double hxi = g.h[0][gi], hyj = g.h[1][gj], hzk = g.h[2][kk];
-      const double wx = g.dw[0][gi] * g.ih[1][gj] * g.ih[2][kk];
-      const double wy = g.dw[1][gj] * g.ih[2][kk] * g.ih[0][gi];
-      const double wz = g.dw[2][kk] * g.ih[0][gi] * g.ih[1][gj];
+    if (gi >= 0 && gj >= 0 && kk >= 0 && gi <= g.nx && gj <= g.ny && kk <= g.nz) {
+      const double hxi = wxh[li], hyj = wyh[lj], hzk = wzh[pl];
+      const double wx = wxd[li] * wyi[lj] * wzi[pl];
+      const double wy = wyd[lj] * wzi[pl] * wxi[li];
+      const double wz = wzd[pl] * wxi[li] * wyi[lj];
       const int a = pl, b = pl + 1;  // planes kk and kk+1 in sp
       fx = wx * (hyj * sp[a][1][lj][li] + hzk * sp[a][2][lj + 1][li] - hyj * sp[b][1][lj][li] - hzk * sp[a][2][lj][li]);
       fy = wy * (hzk * sp[a][2][lj][li] + hxi * sp[b][0][lj][li] - hzk * sp[a][2][lj][li + 1] - hxi * sp[a][0][lj][li]);
@@ -1099,14 +1124,15 @@ struct TileShape {
 };
 static const TileShape kSeedTiles[] = {{32, 4, 2}, {32, 4, 4}, {64, 2, 2}, {64, 2, 4}, {64, 4, 4},
                                        {64, 4, 8}, {32, 8, 4}, {32, 2, 2}, {64, 1, 4}, {64, 2, 8},
-                                       {32, 4, 2}, {32, 4, 4}, {64, 2, 2}, {64, 4, 2}, {32, 8, 2}, {64, 2, 4}};
+                                       {32, 4, 2}, {32, 4, 4}, {64, 2, 2}, {64, 4, 2}, {32, 8, 2}, {64, 2, 4},
+                                       {64, 4, 1}, {64, 8, 1}, {32, 8, 1}, {64, 2, 1}};
 static int g_seed_tile = -1;
 
 static int pick_seed_tile(const GridArgs& g) {
   if (g_seed_tile < 0) {
     const char* env = getenv("TEM_SEED_TILE");
-    g_seed_tile = env ? atoi(env) : 13;
-    if (g_seed_tile < 0 || g_seed_tile >= (int)(sizeof(kSeedTiles) / sizeof(kSeedTiles[0]))) g_seed_tile = 13;
+    g_seed_tile = env ? atoi(env) : 17;
+    if (g_seed_tile < 0 || g_seed_tile >= (int)(sizeof(kSeedTiles) / sizeof(kSeedTiles[0]))) g_seed_tile = 17;
   }
   (void)g;
   return g_seed_tile;
@@ -1145,6 +1171,10 @@ void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold,
     TEM_SEED_CASE(13, 64, 4, 2)
     TEM_SEED_CASE(14, 32, 8, 2)
     TEM_SEED_CASE(15, 64, 2, 4)
+    TEM_SEED_CASE(16, 64, 4, 1)
+    TEM_SEED_CASE(17, 64, 8, 1)
+    TEM_SEED_CASE(18, 32, 8, 1)
+    TEM_SEED_CASE(19, 64, 2, 1)
   }
 #undef TEM_SEED_CASE
 }
