@@ -72,6 +72,50 @@ def cpu_baseline(wl, s, seconds):
                       "system does not fit in memory)" % (info["iterations"], dt)}
 
 
+def serve_bench(args):
+    """Serving: the first N requests of the seeded trace, all sharing the poles
+    of the 40-channel set; latency = arrival to result, queueing included."""
+    import torch
+    import tem_workloads as W
+    from paper_2506_11657_amd import tem
+    from paper_2506_11657_amd.serve import Request, Server, summarize
+    trace = W.serving_trace(seed=7, n_req=args.serve)
+    t = W.log_channels(1e-6, 1e-2, 40)
+    xi, c, err = tem.poles(t, 44)
+    torch.cuda.set_device(0)
+    reqs = []
+    for i, q in enumerate(trace):
+        wl = W.serving_request(q["n"], q["n_src"], q["seed"])
+        r = Request(rid=i, kind=q["kind"], workload=wl, arrival=q["arrival"])
+        if r.kind == "adjoint":
+            # misfit 0.5 ||d||^2 (zero observed data): the adjoint sources are the
+            # predicted data themselves, so every receiver and channel is active
+            r.d_obs = np.zeros((len(wl.loops), len(t), len(wl.receivers)))
+        reqs.append(r)
+    results = {}
+    modes = [("batched", args.serve_max_active)] + ([("one_at_a_time", 1)] if args.serve_compare else [])
+    for label, active in modes:
+        for r in reqs:
+            r.admitted = r.finished = r.data = r.grad = r.error = None
+            r.stats = {}
+        srv = Server(xi, c, max_active=active, hbm_budget=200 << 30, verbose=True)
+        t0 = time.perf_counter()
+        srv.run(reqs, realtime=True)
+        wall = time.perf_counter() - t0
+        results[label] = summarize(reqs, wall)
+        print("%s: %s" % (label, results[label]), file=sys.stderr, flush=True)
+    b = results["batched"]
+    out = {"metric": METRIC, "value": b["models_per_s"], "unit": "models/s", "n_gpus": 1,
+           "steps": len(reqs), "warmup": 0, "ms_per_step": 1e3 * b["makespan_s"] / max(len(reqs), 1),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded trace)",
+           "config": {"workload": "serving trace (grids 32/48/64/96, forward+adjoint, 1-4 loops, 200 req/s)",
+                      "requests": len(reqs), "max_active": args.serve_max_active},
+           "latency_ms": {"p50": b["p50_ms"], "p99": b["p99_ms"]},
+           "serving": results}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +126,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fields", action="store_true")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="instead of the forward benchmark, serve the first N requests of the seeded "
+                         "200 req/s trace (grids 32..96, forward and adjoint, 1-4 loops)")
+    ap.add_argument("--serve-max-active", type=int, default=4)
+    ap.add_argument("--serve-compare", action="store_true",
+                    help="also serve the same trace one request at a time (no overlap)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -91,6 +141,8 @@ def main():
     import torch
     import tem_workloads as W
     from paper_2506_11657_amd import tem
+    if args.serve:
+        return serve_bench(args)
 
     wl = {"graded64": W.cfg_graded64, "plain16": W.cfg_plain16, "blocky128": W.cfg_blocky128}[args.config]()
     xi, c, err = tem.poles(wl.t, wl.degree)

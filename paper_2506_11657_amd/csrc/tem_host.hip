@@ -19,6 +19,7 @@ static_assert(sizeof(tem::SolveHead) <= 4096, "pinned head buffer");
 namespace {
 
 thread_local std::string g_global_error;
+constexpr int kAdjointMultishiftMaxRx = 12;  // adjoint by per-receiver multi-shift solves up to this many receivers
 
 struct DevBuf {
   void* p = nullptr;
@@ -53,6 +54,7 @@ struct tem_ctx {
   // stored forward state for the adjoint
   bool fwd_valid = false;
   int fwd_J = 0, fwd_T = 0, fwd_nsrc = 0, fwd_nrx = 0;
+  double fwd_s0 = 0.0;
   std::vector<double> fwd_xi, fwd_c;
   std::vector<tem_receiver> fwd_rx;
   std::vector<tem_loop> fwd_src;
@@ -123,6 +125,18 @@ void loop_source(const tem_ctx* c, const tem_loop& L, std::vector<double>& f) {
     f[1 * nn + node_index(c, L.i1, j, c->ks)] += L.current * c->hy[j];
     f[1 * nn + node_index(c, L.i0, j, c->ks)] -= L.current * c->hy[j];
   }
+}
+
+// Receiver row q (dB_z/dt = q . u) in the node-padded layout: minus the
+// circulation around the surface z-face of column (i, j) over its area.
+void receiver_row(const tem_ctx* c, const tem_receiver& r, std::vector<double>& q) {
+  const long long nn = c->g.nn;
+  std::fill(q.begin(), q.end(), 0.0);
+  const double hx = c->hx[r.i], hy = c->hy[r.j], inva = -1.0 / (hx * hy);
+  q[0 * nn + node_index(c, r.i, r.j, c->ks)] += hx * inva;
+  q[1 * nn + node_index(c, r.i + 1, r.j, c->ks)] += hy * inva;
+  q[0 * nn + node_index(c, r.i, r.j + 1, c->ks)] -= hx * inva;
+  q[1 * nn + node_index(c, r.i, r.j, c->ks)] -= hy * inva;
 }
 
 int check_loops(tem_ctx* ctx, const tem_loop* src, int n_src) {
@@ -531,6 +545,7 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
   ctx->fwd_rx.assign(rx, rx + n_rx);
   ctx->fwd_src.assign(src, src + n_src);
   ctx->fwd_opts = o;
+  ctx->fwd_s0 = s0;
   S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   for (int i = 0; i < 4; ++i) {
     S.kernel_ms[i] = ctx->prof_ms[i];
@@ -613,7 +628,7 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
   if ((rc = ensure(ctx, H, vb)) || (rc = ensure(ctx, Mu, vb)) || (rc = ensure(ctx, Rr, vb)) ||
       (rc = ensure(ctx, Pb, 2 * vb)) || (rc = ensure(ctx, Q, vb)) || (rc = ensure(ctx, z, ctx->n3 * sizeof(double))) ||
       (rc = ensure(ctx, gd, ncell * sizeof(double))) || (rc = ensure(ctx, gam, 2 * (size_t)J * n_rx * sizeof(double))) ||
-      (rc = ensure(ctx, cst, tem::cocg_state_bytes())) ||
+      (rc = ensure(ctx, cst, std::max(tem::cocg_state_bytes(), (size_t)(2 * TEM_MAX_SHIFTS * sizeof(double))))) ||
       (rc = ensure(ctx, part, (size_t)tem::cocg_partials(ctx->g, J) * sizeof(double)))) {
     cleanup();
     return rc;
@@ -641,6 +656,51 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
         gamma[2 * ((size_t)j * n_rx + r) + 1] = gi;
       }
     e = hipMemcpyAsync(gam.p, gamma.data(), gamma.size() * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) break;
+    if (n_rx <= kAdjointMultishiftMaxRx) {
+      // lambda_j = sum_r gamma_jr (K + s_j M)^-1 q_r: one multi-shift solve per
+      // receiver row (all shifts share its Krylov recurrence), combined on the device
+      e = hipMemsetAsync(Mu.p, 0, vb, st);
+      std::vector<double> qrow(ctx->n3);
+      std::vector<double> sre(J), sim(J);
+      for (int j = 0; j < J; ++j) {
+        sre[j] = -ctx->fwd_xi[2 * j];
+        sim[j] = -ctx->fwd_xi[2 * j + 1];
+      }
+      std::vector<double> gcol(2 * (size_t)J);
+      for (int r = 0; r < n_rx && e == hipSuccess; ++r) {
+        receiver_row(ctx, ctx->fwd_rx[r], qrow);
+        e = hipMemcpyAsync(ctx->f.p, qrow.data(), ctx->n3 * sizeof(double), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) break;
+        tem::launch_scale(ctx->n3, ctx->d_dinv, (const double*)ctx->f.p, (double*)ctx->gvec.p, st);
+        SolveState shs;
+        double secs = 0.0;
+        int r2 = multishift_solve(ctx, sre, sim, ctx->fwd_s0, o, (double2*)H.p, shs, secs);
+        if (r2 == TEM_ENOCONV) S.converged = 0;
+        else if (r2 != TEM_OK) {
+          cleanup();
+          return r2;
+        }
+        S.iterations += shs.k;
+        for (int j = 0; j < J; ++j) {
+          S.iters_per_shift[j] += shs.iters[j];
+          S.est_res[j] = std::max(S.est_res[j], shs.est[j] / std::sqrt(shs.rr0));
+          S.unknown_updates += (double)ctx->nunk * shs.iters[j];
+          gcol[2 * j] = gamma[2 * ((size_t)j * n_rx + r)];
+          gcol[2 * j + 1] = gamma[2 * ((size_t)j * n_rx + r) + 1];
+        }
+        e = hipMemcpyAsync(cst.p, gcol.data(), gcol.size() * sizeof(double), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) {
+          tem::launch_caxpy_shifts(ctx->g, J, (const double*)cst.p, (const double2*)H.p, (double2*)Mu.p, st);
+          e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(st);  // gcol is reused by the next receiver
+      }
+      if (e != hipSuccess) break;
+      tem::launch_grad_edges(ctx->g, J, (const double2*)Mu.p, (const double2*)ctx->Y[s].p, ctx->d_dinv, shd,
+                             shd + TEM_MAX_SHIFTS, (double*)z.p, st);
+      continue;
+    }
     if (e == hipSuccess) e = hipMemsetAsync(H.p, 0, vb, st);
     std::memset(hs.get(), 0, sizeof(tem::CocgState));
     hs->J = J;

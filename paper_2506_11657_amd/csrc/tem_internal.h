@@ -133,6 +133,8 @@ void launch_cocg_update(const GridArgs& g, int J, double2* Mu, double2* Rr, cons
 void launch_grad_edges(const GridArgs& g, int J, const double2* Mu, const double2* Y, const double* dinv,
                        const double* sre, const double* sim, double* z, hipStream_t s);
 void launch_grad_cells(const GridArgs& g, const double* sigma, const double* z, double* grad, hipStream_t s);
+void launch_caxpy_shifts(const GridArgs& g, int J, const double* gamma, const double2* Yr, double2* Mu,
+                         hipStream_t s);
 
 // ---- host RKFIT (tem_rkfit.cpp) --------------------------------------------
 struct RkfitResult {

@@ -1081,6 +1081,21 @@ __global__ void k_grad_cells(GridArgs g, const double* __restrict__ sigma, const
   grad[c] = -0.25 * sigma[c] * vol * s;
 }
 
+// Mu_j += gamma_j Yr_j for all shifts j (complex scalar times complex vector)
+__global__ void k_caxpy_shifts(long long n3, int J, const double* __restrict__ gamma, const double2* __restrict__ Yr,
+                               double2* Mu) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= n3) return;
+  for (int j = 0; j < J; ++j) {
+    const double gr = gamma[2 * j], gi = gamma[2 * j + 1];
+    const double2 y = Yr[(long long)j * n3 + e];
+    double2 m = Mu[(long long)j * n3 + e];
+    m.x += gr * y.x - gi * y.y;
+    m.y += gr * y.y + gi * y.x;
+    Mu[(long long)j * n3 + e] = m;
+  }
+}
+
 int grid_1d(long long n, int threads, int cap) {
   long long b = (n + threads - 1) / threads;
   if (b < 1) b = 1;
@@ -1126,16 +1141,16 @@ static const TileShape kSeedTiles[] = {{32, 4, 2}, {32, 4, 4}, {64, 2, 2}, {64, 
                                        {64, 4, 8}, {32, 8, 4}, {32, 2, 2}, {64, 1, 4}, {64, 2, 8},
                                        {32, 4, 2}, {32, 4, 4}, {64, 2, 2}, {64, 4, 2}, {32, 8, 2}, {64, 2, 4},
                                        {64, 4, 1}, {64, 8, 1}, {32, 8, 1}, {64, 2, 1}};
-static int g_seed_tile = -1;
-
 static int pick_seed_tile(const GridArgs& g) {
-  if (g_seed_tile < 0) {
+  // fixed per process (thread-safe static initialization); TEM_SEED_TILE overrides
+  static const int v = [] {
     const char* env = getenv("TEM_SEED_TILE");
-    g_seed_tile = env ? atoi(env) : 17;
-    if (g_seed_tile < 0 || g_seed_tile >= (int)(sizeof(kSeedTiles) / sizeof(kSeedTiles[0]))) g_seed_tile = 17;
-  }
+    int t = env ? atoi(env) : 17;
+    if (t < 0 || t >= (int)(sizeof(kSeedTiles) / sizeof(kSeedTiles[0]))) t = 17;
+    return t;
+  }();
   (void)g;
-  return g_seed_tile;
+  return v;
 }
 
 static dim3 seed_stencil_grid(const GridArgs& g) {
@@ -1305,6 +1320,12 @@ void launch_grad_edges(const GridArgs& g, int J, const double2* Mu, const double
   const long long n3 = 3 * g.nn;
   hipLaunchKernelGGL(k_grad_edges, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, n3, J, Mu, Y, dinv, sre, sim,
                      z);
+}
+
+void launch_caxpy_shifts(const GridArgs& g, int J, const double* gamma, const double2* Yr, double2* Mu,
+                         hipStream_t s) {
+  const long long n3 = 3 * g.nn;
+  hipLaunchKernelGGL(k_caxpy_shifts, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, n3, J, gamma, Yr, Mu);
 }
 
 void launch_grad_cells(const GridArgs& g, const double* sigma, const double* z, double* grad, hipStream_t s) {

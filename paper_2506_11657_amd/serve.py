@@ -1,0 +1,150 @@
+"""Request loop for forward and adjoint TEM solves on one GPU.
+
+Requests (a grid, a conductivity model, 1-4 loops, receivers; forward or
+adjoint) arrive over time.  A scheduler admits a request when its device
+footprint fits in the HBM budget and a slot is free; every admitted request
+runs on its own library context and HIP stream in a worker thread (the C
+calls release the GIL), so the graph-replayed solver blocks of different
+requests are in flight on the device at the same time and a request that
+arrives while others run is admitted as soon as memory and a slot free up.
+All requests share one pole/residue set (the channels are the same).
+
+Each request's arithmetic is independent of the others (its own buffers,
+fixed-order reductions), so its result is bitwise the same alone or in any
+mix.
+"""
+from __future__ import annotations
+
+import sys
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import tem
+
+
+def footprint_bytes(nx, ny, nz, J, n_src, kind, block=32):
+    """Device bytes a request needs: operator arrays, the Krylov workspace of
+    one multi-shift solve (residual ring, seed vectors, per-shift x_j and p_j)
+    and, for the adjoint, the stored solutions of every source plus the J
+    complex COCG vectors."""
+    n3 = 3 * (nx + 1) * (ny + 1) * (nz + 1)
+    ops = 8 * n3 * 3 + 8 * nx * ny * nz
+    solve = 8 * n3 * (block + 4) + 16 * n3 * J * 2 + 16 * n3
+    keep = 16 * n3 * J * n_src if kind == "adjoint" else 0
+    adj = 16 * n3 * J * 6 + 8 * n3 if kind == "adjoint" else 0
+    return ops + solve + keep + adj
+
+
+@dataclass
+class Request:
+    rid: int
+    kind: str                    # "forward" or "adjoint"
+    workload: object             # tem_workloads.Workload
+    arrival: float = 0.0         # seconds after the trace start
+    d_obs: np.ndarray = None     # adjoint: observed data (n_src, T, n_rx)
+    footprint: int = 0
+    # results
+    admitted: float = None
+    finished: float = None
+    data: np.ndarray = None
+    grad: np.ndarray = None
+    stats: dict = field(default_factory=dict)
+    error: str = None
+
+    @property
+    def latency(self):
+        return None if self.finished is None else self.finished - self.arrival
+
+
+class Server:
+    def __init__(self, xi, c, device=0, hbm_budget=64 << 30, max_active=4, rtol=0.0, verbose=False):
+        self.verbose = verbose
+        self.xi, self.c = np.asarray(xi), np.asarray(c)
+        self.device = device
+        self.budget = int(hbm_budget)
+        self.max_active = int(max_active)
+        self.rtol = rtol
+        self._lock = threading.Condition()
+        self._used = 0
+        self._active = 0
+        self._threads = []
+
+    def _run(self, req: Request, t0: float):
+        wl = req.workload
+        ctx = None
+        try:
+            ctx = tem.Context(wl.hx, wl.hy, wl.hz, wl.k_s, device=self.device)
+            ctx.set_conductivity(wl.sigma)
+            keep = req.kind == "adjoint"
+            data, st = ctx.forward(wl.loops, wl.receivers, self.xi, self.c, keep_solutions=keep, rtol=self.rtol)
+            req.data = data
+            req.stats["forward"] = {"iterations": st["iterations"], "unknown_updates": st["unknown_updates"]}
+            if keep:
+                w = data - req.d_obs
+                grad, sa = ctx.adjoint(w)
+                req.grad = grad
+                req.stats["adjoint"] = {"iterations": sa["iterations"], "unknown_updates": sa["unknown_updates"]}
+        except Exception as e:  # reported per request; the loop keeps serving
+            req.error = repr(e)
+        finally:
+            if ctx is not None:
+                ctx.close()
+            req.finished = time.perf_counter() - t0
+            if self.verbose:
+                wl = req.workload
+                print("request %d (%s, %dx%dx%d, %d loops) done at %.2f s, latency %.2f s%s"
+                      % (req.rid, req.kind, len(wl.hx), len(wl.hy), len(wl.hz), len(wl.loops), req.finished,
+                         req.latency, "" if req.error is None else " ERROR " + req.error),
+                      file=sys.stderr, flush=True)
+            with self._lock:
+                self._used -= req.footprint
+                self._active -= 1
+                self._lock.notify_all()
+
+    def run(self, requests, realtime=True):
+        """Serve the requests in arrival order; with realtime, a request is not
+        admitted before its arrival time.  Returns the requests with results
+        and timestamps (seconds from the start)."""
+        J = len(self.xi)
+        for r in requests:
+            wl = r.workload
+            r.footprint = footprint_bytes(len(wl.hx), len(wl.hy), len(wl.hz), J, len(wl.loops), r.kind)
+            if r.footprint > self.budget:
+                r.error = "TEM_ENOMEM: request footprint %d exceeds the budget %d" % (r.footprint, self.budget)
+        t0 = time.perf_counter()
+        for r in sorted(requests, key=lambda q: q.arrival):
+            if r.error:
+                r.finished = r.arrival
+                continue
+            if realtime:
+                wait = r.arrival - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+            with self._lock:
+                while self._active >= self.max_active or self._used + r.footprint > self.budget:
+                    self._lock.wait()
+                self._active += 1
+                self._used += r.footprint
+            r.admitted = time.perf_counter() - t0
+            th = threading.Thread(target=self._run, args=(r, t0), daemon=True)
+            th.start()
+            self._threads.append(th)
+        for th in self._threads:
+            th.join()
+        self._threads = []
+        return requests
+
+
+def summarize(requests, wall):
+    done = [r for r in requests if r.error is None and r.finished is not None]
+    lat = np.array([r.latency for r in done]) if done else np.zeros(1)
+    upd = sum(r.stats.get("forward", {}).get("unknown_updates", 0.0) +
+              r.stats.get("adjoint", {}).get("unknown_updates", 0.0) for r in done)
+    return {"completed": len(done), "failed": len(requests) - len(done),
+            "models_per_s": len(done) / wall if wall > 0 else 0.0,
+            "unknown_updates_per_s": upd / wall if wall > 0 else 0.0,
+            "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+            "makespan_s": wall}

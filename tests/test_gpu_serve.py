@@ -1,0 +1,72 @@
+"""Serving loop: continuous admission by HBM footprint, requests overlapping
+on the device, and each result identical alone and in the mix."""
+import numpy as np
+import pytest
+
+import tem_workloads as W
+from oracle import rkfit
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tem():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_11657_amd import tem as T
+    T.lib()
+    return T
+
+
+def _requests(n=5):
+    from paper_2506_11657_amd.serve import Request
+    t = W.log_channels(1e-5, 1e-3, 12)
+    reqs = []
+    rng = np.random.default_rng(7)
+    for i in range(n):
+        wl = W.small_case(8 + 2 * (i % 3), seed=100 + i, t=t)
+        kind = "adjoint" if i % 2 else "forward"
+        r = Request(rid=i, kind=kind, workload=wl, arrival=0.01 * i)
+        if kind == "adjoint":
+            r.d_obs = np.zeros((1, len(t), len(wl.receivers)))
+        reqs.append(r)
+    return reqs, t
+
+
+def test_alone_equals_mix_bitwise(tem):
+    from paper_2506_11657_amd.serve import Server, summarize
+    reqs, t = _requests()
+    fit = rkfit.rkfit(t, 18)
+    s, C = rkfit.shifts_and_coefficients(fit)
+    alone = Server(-s, C, max_active=1).run(_requests()[0], realtime=False)
+    mix_srv = Server(-s, C, max_active=4)
+    import time
+    t0 = time.perf_counter()
+    mix = mix_srv.run(reqs, realtime=True)
+    summ = summarize(mix, time.perf_counter() - t0)
+    assert summ["completed"] == len(reqs)
+    for a, m in zip(alone, mix):
+        assert a.error is None and m.error is None, (a.error, m.error)
+        assert np.array_equal(a.data, m.data)
+        if a.kind == "adjoint":
+            assert np.array_equal(a.grad, m.grad)
+
+
+def test_admission_by_footprint(tem):
+    """A budget that holds one request at a time serializes them; a request
+    larger than the budget is rejected without running."""
+    from paper_2506_11657_amd.serve import Server, footprint_bytes
+    reqs, t = _requests(3)
+    fit = rkfit.rkfit(t, 18)
+    s, C = rkfit.shifts_and_coefficients(fit)
+    fps = [footprint_bytes(len(r.workload.hx), len(r.workload.hy), len(r.workload.hz), len(s), 1, r.kind) for r in reqs]
+    srv = Server(-s, C, max_active=8, hbm_budget=max(fps))
+    out = srv.run(reqs, realtime=False)
+    spans = sorted((r.admitted, r.finished) for r in out)
+    for (a0, f0), (a1, f1) in zip(spans, spans[1:]):
+        assert a1 >= f0 - 1e-3   # never two requests resident at once
+    big = _requests(1)[0]
+    srv2 = Server(-s, C, hbm_budget=1 << 20)
+    r = srv2.run(big, realtime=False)[0]
+    assert r.error is not None and "ENOMEM" in r.error
