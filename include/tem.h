@@ -73,14 +73,26 @@ typedef struct { int i0, i1, j0, j1; double current; } tem_loop;
 typedef struct { int i, j; } tem_receiver;
 
 typedef struct {
-  int precision;     /* 0: FP64 Krylov sweeps; 1: FP32 sweeps + FP64 residual refinement */
-  double rtol;       /* per-shift stop: |zeta_j| ||r||_2 <= rtol ||g||_2 in the scaled system;
-                        <= 0 selects 1e-12 (FP64) */
+  int precision;     /* 0: FP64 Krylov sweeps.  1: the multi-shift sweep keeps the complex
+                        per-shift vectors x_j, p_j in FP32 (the shared real seed recurrence
+                        stays FP64) and stops at a scaled residual of 1e-6; FP64 residuals
+                        rho_j then drive refinement passes, each a batched COCG with complex
+                        FP32 vectors on (K + s_j M) d_j = rho_j to a 1e-2 reduction and
+                        x_j += d_j in FP64; a correction that does not lower a shift's FP64
+                        residual is taken back and that shift is not refined again.  On
+                        stiff grids (seed solves of 1e4+ iterations) FP32 Krylov corrections
+                        stagnate and the call returns TEM_ENOCONV with the best iterate.
+                        Contraction and receivers are FP64 in both. */
+  double rtol;       /* per-shift target in the scaled system y = M^1/2 x, g = M^-1/2 f:
+                        precision 0 stops shift j when |zeta_j| ||r||_2 <= rtol ||g||_2
+                        (<= 0 selects 1e-12); precision 1 refines until the FP64 residual
+                        ||g - (A + s_j) y_j||_2 <= rtol ||g||_2 (<= 0 selects 1e-8) */
   int max_iter;      /* cap on seed iterations per solve; <= 0 selects 2000000 */
   int block;         /* iterations between deferred shift updates (1..64); <= 0 selects 32 */
   double seed_shift; /* real seed shift of the shared recurrence; <= 0 selects
                         max(min_j Re s_j, 1e-3 min_j |s_j|), s_j = -xi_j */
-  int refine_max;    /* precision 1: cap on refinement passes; <= 0 selects 8 */
+  int refine_max;    /* precision 1: cap on refinement passes; <= 0 selects 8; a shift
+                        still above rtol after the cap gives TEM_ENOCONV */
   int keep_solutions;/* nonzero: keep X on the device for tem_adjoint / tem_solutions */
   int profile;       /* nonzero: time every solver kernel launch with HIP events on the
                         context stream (fills kernel_ms / kernel_launches of tem_stats) */

@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -20,6 +21,13 @@ namespace {
 
 thread_local std::string g_global_error;
 constexpr int kAdjointMultishiftMaxRx = 12;  // adjoint by per-receiver multi-shift solves up to this many receivers
+// precision 1: the sweep with complex FP32 shift vectors stops at this scaled
+// residual (their storage rounding sits near it); FP64 residual refinement then
+// drives every shift to the requested rtol (default kRefineTarget), each pass
+// reducing the correction system's residual by kRefinePassTol
+constexpr double kSweepTolFP32 = 1e-6;
+constexpr double kRefineTarget = 1e-8;
+constexpr double kRefinePassTol = 1e-2;
 
 struct DevBuf {
   void* p = nullptr;
@@ -50,6 +58,7 @@ struct tem_ctx {
   double* d_partials = nullptr;
   unsigned int* d_counters = nullptr;
   DevBuf R, pbuf, q, gvec, gc, f, P, C, rx, data, res, cpart, sh;
+  DevBuf y32, refine, cst, cocg_part;  // precision 1: FP32 shift solutions, refinement COCG vectors and state
   std::vector<DevBuf> Y;  // per source (kept) or one
   // stored forward state for the adjoint
   bool fwd_valid = false;
@@ -66,6 +75,15 @@ struct tem_ctx {
 };
 
 namespace {
+
+// TEM_VERBOSE=1: progress lines on stderr from long solves
+bool verbose() {
+  static const bool v = [] {
+    const char* e = getenv("TEM_VERBOSE");
+    return e && *e && *e != '0';
+  }();
+  return v;
+}
 
 int fail(tem_ctx* ctx, int code, const std::string& msg) {
   if (ctx) ctx->err = msg;
@@ -161,7 +179,7 @@ int order_after_caller(tem_ctx* ctx) {
 tem_solve_opts resolve_opts(const tem_solve_opts* o) {
   tem_solve_opts r{};
   if (o) r = *o;
-  if (!(r.rtol > 0.0)) r.rtol = 1e-12;
+  if (!(r.rtol > 0.0)) r.rtol = r.precision == 1 ? kRefineTarget : 1e-12;
   if (r.max_iter <= 0) r.max_iter = 2000000;
   if (r.block <= 0) r.block = 32;
   if (r.refine_max <= 0) r.refine_max = 8;
@@ -177,8 +195,11 @@ int block_length(int requested, int J) {
 
 // One multi-shift solve (all J shifts, one right-hand side) on the device.
 // Y receives the scaled solutions y_j = M^{1/2} x_j (node-padded, complex).
+// V = double2 (FP64 path) or float2 (complex FP32 shift vectors, precision 1);
+// P is J node-padded vectors of V, as Y.
+template <typename V>
 int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const std::vector<double>& shifts_im,
-                     double s0, const tem_solve_opts& o, double2* Y, SolveState& host_state, double& seconds) {
+                     double s0, const tem_solve_opts& o, V* Y, V* P, SolveState& host_state, double& seconds) {
   const int J = (int)shifts_re.size();
   const int B = block_length(o.block, J);
   hipStream_t st = ctx->work;
@@ -188,11 +209,9 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
   if ((rc = ensure(ctx, ctx->R, (size_t)B * ctx->n3 * sizeof(double)))) return rc;
   if ((rc = ensure(ctx, ctx->pbuf, 2 * ctx->n3 * sizeof(double)))) return rc;
   if ((rc = ensure(ctx, ctx->q, ctx->n3 * sizeof(double)))) return rc;
-  if ((rc = ensure(ctx, ctx->P, (size_t)J * ctx->n3 * sizeof(double2)))) return rc;
   double* R = (double*)ctx->R.p;
   double* pb = (double*)ctx->pbuf.p;
   double* q = (double*)ctx->q.p;
-  double2* P = (double2*)ctx->P.p;
 
   std::unique_ptr<SolveState> hs(new SolveState());
   std::memset(hs.get(), 0, sizeof(SolveState));
@@ -266,6 +285,7 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
   bool done = false;
   hipError_t lerr = hipSuccess;
   int nblock = 0;
+  double next_report = 10.0;
   while (!done && k < o.max_iter) {
     const bool sample = o.profile && (nblock++ % kProfileEvery == 0);
     if (exec && !sample) lerr = hipGraphLaunch(exec, st);
@@ -295,6 +315,13 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     int n_active = 0;
     for (int j = 0; j < J; ++j) n_active += head.active[j];
     if (n_active == 0) done = true;
+    if (verbose()) {
+      const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (el >= next_report) {
+        fprintf(stderr, "[tem] multi-shift: %d iterations, %d of %d shifts active, %.1f s\n", k, n_active, J, el);
+        next_report = el + 10.0;
+      }
+    }
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
   if (exec) (void)hipGraphExecDestroy(exec);
@@ -307,6 +334,61 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
   for (int j = 0; j < J; ++j)
     if (host_state.active[j]) return fail(ctx, TEM_ENOCONV, "max_iter reached before every shift converged");
   return TEM_OK;
+}
+
+// Batched COCG on (A + s_j) mu_j = h_j for the J shifts in ctx->sh, vectors
+// of V storage (Mu, Rr, P0, P1, Q: J node-padded vectors each); stops shift j
+// when |r_j| <= rtol |h_j|.  Shifts with h_j = 0 stay inactive (mu_j = 0).
+template <typename V>
+int cocg_solve(tem_ctx* ctx, int J, const double2* H, V* Mu, V* Rr, V* P0, V* P1, V* Q, double rtol, int max_iter,
+               tem::CocgState& hs, int& iterations, const int* caps = nullptr) {
+  hipStream_t st = ctx->work;
+  int rc;
+  if ((rc = ensure(ctx, ctx->cst, tem::cocg_state_bytes())) ||
+      (rc = ensure(ctx, ctx->cocg_part, (size_t)tem::cocg_partials(ctx->g, J) * sizeof(double))))
+    return rc;
+  const double* shd = (const double*)ctx->sh.p;
+  std::memset(&hs, 0, sizeof(tem::CocgState));
+  hs.J = J;
+  hs.tol2 = rtol * rtol;
+  for (int j = 0; j < J; ++j) hs.cap[j] = caps ? std::min(caps[j], max_iter) : max_iter;
+  HIPCHK(ctx, hipMemcpyAsync(ctx->cst.p, &hs, sizeof(tem::CocgState), hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemsetAsync(ctx->d_counters + 4, 0, 4 * sizeof(unsigned int), st));
+  double* partials = (double*)ctx->cocg_part.p;
+  tem::launch_cocg_init(ctx->g, J, H, Mu, Rr, P0, partials, ctx->d_counters + 4, ctx->cst.p, st);
+  int it = 0;
+  const int chunk = 32;
+  hipError_t e = hipSuccess;
+  iterations = 0;
+  const auto t0 = std::chrono::steady_clock::now();
+  double next_report = 10.0;
+  while (it < max_iter) {
+    for (int i = 0; i < chunk; ++i, ++it) {
+      V* Pold = (it & 1) ? P1 : P0;
+      V* Pnew = (it & 1) ? P0 : P1;
+      tem::launch_cocg_stencil(ctx->g, J, Rr, Pold, Pnew, Q, ctx->d_dinv, shd, shd + TEM_MAX_SHIFTS, partials,
+                               ctx->d_counters + 5, ctx->cst.p, st);
+      tem::launch_cocg_update(ctx->g, J, Mu, Rr, Pnew, Q, partials, ctx->d_counters + 6, ctx->cst.p, st);
+    }
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&hs, ctx->cst.p, sizeof(tem::CocgState), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(ctx, TEM_EHIP, std::string("COCG: ") + hipGetErrorString(e));
+    iterations = it;
+    if (hs.breakdown) return fail(ctx, TEM_EBREAKDOWN, "COCG breakdown");
+    if (hs.n_active == 0) break;
+    if (verbose()) {
+      const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (el >= next_report) {
+        fprintf(stderr, "[tem] COCG: %d iterations, %d of %d systems active, %.1f s\n", it, hs.n_active, J, el);
+        next_report = el + 10.0;
+      }
+    }
+  }
+  // a shift stopped by its iteration cap has not converged
+  bool capped = hs.n_active > 0;
+  for (int j = 0; j < J; ++j) capped |= hs.iters[j] >= hs.cap[j] && hs.rn2[j] > hs.tol2 * hs.hn2[j];
+  return capped ? fail(ctx, TEM_ENOCONV, "COCG did not reach rtol within its iteration cap") : TEM_OK;
 }
 
 }  // namespace
@@ -444,7 +526,8 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
     if (!std::isfinite(c[i])) return fail(ctx, TEM_EINVAL, "non-finite residue");
   HIPCHK(ctx, hipSetDevice(ctx->device));
   const tem_solve_opts o = resolve_opts(opts);
-  if (o.precision != 0) return fail(ctx, TEM_EINVAL, "precision 1 is not available in this build");
+  if (o.precision != 0 && o.precision != 1)
+    return fail(ctx, TEM_EINVAL, "precision must be 0 (FP64) or 1 (FP32 sweeps + FP64 refinement)");
   double s0 = o.seed_shift;
   if (!(s0 > 0.0)) {
     double minre = 1e300, minabs = 1e300;
@@ -462,6 +545,8 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
   for (int s = 0; s < nY; ++s)
     if ((rc = ensure(ctx, ctx->Y[s], ysz))) return rc;
   if ((rc = ensure(ctx, ctx->gvec, ctx->n3 * sizeof(double)))) return rc;
+  if ((rc = ensure(ctx, ctx->P, (size_t)J * ctx->n3 * sizeof(double2)))) return rc;
+  if (o.precision == 1 && (rc = ensure(ctx, ctx->y32, (size_t)J * ctx->n3 * sizeof(float2)))) return rc;
   if ((rc = ensure(ctx, ctx->gc, ctx->n3 * sizeof(double2)))) return rc;
   if ((rc = ensure(ctx, ctx->f, ctx->n3 * sizeof(double)))) return rc;
   if ((rc = ensure(ctx, ctx->C, 2 * (size_t)J * T * sizeof(double)))) return rc;
@@ -499,7 +584,16 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
     HIPCHK(ctx, hipGetLastError());
     SolveState hs;
     double secs = 0.0;
-    int r = multishift_solve(ctx, sre, sim, s0, o, Y, hs, secs);
+    int r;
+    if (o.precision == 1) {
+      // sweep with complex FP32 shift vectors, then y_j widened to FP64
+      tem_solve_opts o32 = o;
+      o32.rtol = std::max(o.rtol, kSweepTolFP32);
+      r = multishift_solve(ctx, sre, sim, s0, o32, (float2*)ctx->y32.p, (float2*)ctx->P.p, hs, secs);
+      if (r == TEM_OK || r == TEM_ENOCONV) tem::launch_accumulate(ctx->g, J, (const float2*)ctx->y32.p, Y, 0, 0, st);
+    } else {
+      r = multishift_solve(ctx, sre, sim, s0, o, Y, (double2*)ctx->P.p, hs, secs);
+    }
     if (r == TEM_ENOCONV) {
       S.converged = 0;
       status = r;
@@ -512,13 +606,85 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
       S.est_res[j] = hs.est[j] / std::sqrt(hs.rr0);
       S.unknown_updates += (double)ctx->nunk * hs.iters[j];
     }
-    // FP64 true residuals ||g - (A + s_j) y_j|| / ||g|| (the P buffer is free now)
+    // FP64 true residuals rho_j = g - (A + s_j) y_j into the P buffer (free
+    // after the sweep) and ||rho_j||^2 into true2
     tem::launch_to_complex(ctx->n3, (const double*)ctx->gvec.p, (double2*)ctx->gc.p, st);
-    tem::launch_cstencil(ctx->g, Y, ctx->n3, ctx->d_dinv, shd, shd + TEM_MAX_SHIFTS, J, (const double2*)ctx->gc.p,
-                         (double2*)ctx->P.p, ctx->n3, (double*)ctx->cpart.p, st);
-    tem::launch_reduce_rows((const double*)ctx->cpart.p, J, cpb, shd + 2 * TEM_MAX_SHIFTS, st);
-    HIPCHK(ctx, hipGetLastError());
-    HIPCHK(ctx, hipMemcpyAsync(true2.data(), shd + 2 * TEM_MAX_SHIFTS, J * sizeof(double), hipMemcpyDeviceToHost, st));
+    auto true_residuals = [&]() -> int {
+      tem::launch_cstencil(ctx->g, Y, ctx->n3, ctx->d_dinv, shd, shd + TEM_MAX_SHIFTS, J, (const double2*)ctx->gc.p,
+                           (double2*)ctx->P.p, ctx->n3, (double*)ctx->cpart.p, st);
+      tem::launch_reduce_rows((const double*)ctx->cpart.p, J, cpb, shd + 2 * TEM_MAX_SHIFTS, st);
+      HIPCHK(ctx, hipGetLastError());
+      HIPCHK(ctx, hipMemcpyAsync(true2.data(), shd + 2 * TEM_MAX_SHIFTS, J * sizeof(double), hipMemcpyDeviceToHost,
+                                 st));
+      HIPCHK(ctx, hipStreamSynchronize(st));
+      return TEM_OK;
+    };
+    if ((rc = true_residuals())) return rc;
+    if (verbose()) {
+      double w = 0.0;
+      for (int j = 0; j < J; ++j) w = std::max(w, std::sqrt(true2[j] / hs.rr0));
+      fprintf(stderr, "[tem] source %d: %d seed iterations in %.2f s, max scaled FP64 residual %.2e\n", s, hs.k, secs,
+              w);
+    }
+    if (o.precision == 1) {
+      // FP64 residual refinement: (A + s_j) d_j = rho_j by batched COCG with
+      // complex FP32 vectors to kRefinePassTol, y_j += d_j in FP64, new rho_j.
+      // A correction that does not lower shift j's FP64 residual is taken back
+      // and the shift is not refined further (FP32 Krylov stagnation); the
+      // passes end when no shift is left to refine.
+      auto rel = [&](int j) { return std::sqrt(true2[j] / hs.rr0); };
+      auto worst = [&]() {
+        double w = 0.0;
+        for (int j = 0; j < J; ++j) w = std::max(w, rel(j));
+        return w;
+      };
+      std::vector<char> stalled(J, 0);
+      // per-shift COCG iteration budget, quartered when a pass is taken back
+      std::vector<int> caps(J, std::min(o.max_iter, std::max(hs.k, 256)));
+      int passes = 0;
+      while (passes < o.refine_max) {
+        unsigned long long todo = 0;
+        for (int j = 0; j < J; ++j)
+          if (!stalled[j] && rel(j) > o.rtol) todo |= 1ull << j;
+        if (!todo) break;
+        const size_t vn = (size_t)J * ctx->n3;
+        if ((rc = ensure(ctx, ctx->refine, 5 * vn * sizeof(float2)))) return rc;
+        for (int j = 0; j < J; ++j)  // a zero right-hand side leaves shift j inactive (d_j = 0)
+          if (!((todo >> j) & 1ull))
+            HIPCHK(ctx, hipMemsetAsync((double2*)ctx->P.p + (size_t)j * ctx->n3, 0, ctx->n3 * sizeof(double2), st));
+        float2* v = (float2*)ctx->refine.p;
+        tem::CocgState cs;
+        int its = 0;
+        const int cap = *std::max_element(caps.begin(), caps.end());
+        int r2 = cocg_solve(ctx, J, (const double2*)ctx->P.p, v, v + vn, v + 2 * vn, v + 3 * vn, v + 4 * vn,
+                            kRefinePassTol, cap, cs, its, caps.data());
+        if (r2 != TEM_OK && r2 != TEM_ENOCONV) return r2;
+        for (int j = 0; j < J; ++j) S.unknown_updates += (double)ctx->nunk * cs.iters[j];
+        const std::vector<double> before = true2;
+        tem::launch_accumulate(ctx->g, J, v, Y, +1, todo, st);
+        ++passes;
+        if ((rc = true_residuals())) return rc;
+        unsigned long long back = 0;
+        for (int j = 0; j < J; ++j)
+          if (((todo >> j) & 1ull) && !(true2[j] < before[j])) {
+            back |= 1ull << j;
+            caps[j] /= 4;
+            if (caps[j] < 32) stalled[j] = 1;
+          }
+        if (back) {
+          tem::launch_accumulate(ctx->g, J, v, Y, -1, back, st);
+          if ((rc = true_residuals())) return rc;
+        }
+        if (verbose())
+          fprintf(stderr, "[tem] refinement pass %d: %d COCG iterations, %d shifts taken back, max scaled FP64 "
+                  "residual %.2e\n", passes, its, __builtin_popcountll(back), worst());
+      }
+      S.refine_passes = std::max(S.refine_passes, passes);
+      if (worst() > o.rtol) {
+        S.converged = 0;
+        status = fail(ctx, TEM_ENOCONV, "FP64 residual refinement did not reach rtol within refine_max passes");
+      }
+    }
     // receivers and (optionally) full fields
     if (n_rx > 0) {
       tem::launch_receivers(ctx->g, Y, J, ctx->d_dinv, (const double*)ctx->C.p, T, (const int*)ctx->rx.p, n_rx,
@@ -620,16 +786,15 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
   hipStream_t st = ctx->work;
   const tem_solve_opts& o = ctx->fwd_opts;
   const size_t vb = (size_t)J * ctx->n3 * sizeof(double2);
-  DevBuf H, Mu, Rr, Pb, Q, z, gd, gam, cst, part;
+  DevBuf H, Mu, Rr, Pb, Q, z, gd, gam, cst;
   auto cleanup = [&]() {
-    for (DevBuf* b : {&H, &Mu, &Rr, &Pb, &Q, &z, &gd, &gam, &cst, &part}) release(*b);
+    for (DevBuf* b : {&H, &Mu, &Rr, &Pb, &Q, &z, &gd, &gam, &cst}) release(*b);
   };
   const long long ncell = (long long)ctx->nx * ctx->ny * ctx->nz;
   if ((rc = ensure(ctx, H, vb)) || (rc = ensure(ctx, Mu, vb)) || (rc = ensure(ctx, Rr, vb)) ||
       (rc = ensure(ctx, Pb, 2 * vb)) || (rc = ensure(ctx, Q, vb)) || (rc = ensure(ctx, z, ctx->n3 * sizeof(double))) ||
       (rc = ensure(ctx, gd, ncell * sizeof(double))) || (rc = ensure(ctx, gam, 2 * (size_t)J * n_rx * sizeof(double))) ||
-      (rc = ensure(ctx, cst, std::max(tem::cocg_state_bytes(), (size_t)(2 * TEM_MAX_SHIFTS * sizeof(double))))) ||
-      (rc = ensure(ctx, part, (size_t)tem::cocg_partials(ctx->g, J) * sizeof(double)))) {
+      (rc = ensure(ctx, cst, (size_t)(2 * TEM_MAX_SHIFTS * sizeof(double))))) {
     cleanup();
     return rc;
   }
@@ -675,7 +840,7 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
         tem::launch_scale(ctx->n3, ctx->d_dinv, (const double*)ctx->f.p, (double*)ctx->gvec.p, st);
         SolveState shs;
         double secs = 0.0;
-        int r2 = multishift_solve(ctx, sre, sim, ctx->fwd_s0, o, (double2*)H.p, shs, secs);
+        int r2 = multishift_solve(ctx, sre, sim, ctx->fwd_s0, o, (double2*)H.p, (double2*)ctx->P.p, shs, secs);
         if (r2 == TEM_ENOCONV) S.converged = 0;
         else if (r2 != TEM_OK) {
           cleanup();
@@ -702,43 +867,21 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
       continue;
     }
     if (e == hipSuccess) e = hipMemsetAsync(H.p, 0, vb, st);
-    std::memset(hs.get(), 0, sizeof(tem::CocgState));
-    hs->J = J;
-    hs->tol2 = o.rtol * o.rtol;
-    if (e == hipSuccess) e = hipMemcpyAsync(cst.p, hs.get(), sizeof(tem::CocgState), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemsetAsync(ctx->d_counters + 4, 0, 4 * sizeof(unsigned int), st);
     if (e != hipSuccess) break;
     tem::launch_adj_rhs(ctx->g, J, n_rx, (const int*)ctx->rx.p, ctx->ks, (const double*)gam.p, ctx->d_dinv,
                         (double2*)H.p, st);
     double2* P0 = (double2*)Pb.p;
     double2* P1 = P0 + (size_t)J * ctx->n3;
-    double* partials = (double*)part.p;
-    tem::launch_cocg_init(ctx->g, J, (const double2*)H.p, (double2*)Mu.p, (double2*)Rr.p, P0, partials,
-                          ctx->d_counters + 4, cst.p, st);
-    int it = 0;
-    const int chunk = 32;
-    while (e == hipSuccess && it < o.max_iter) {
-      for (int i = 0; i < chunk; ++i, ++it) {
-        double2* Pold = (it & 1) ? P1 : P0;
-        double2* Pnew = (it & 1) ? P0 : P1;
-        tem::launch_cocg_stencil(ctx->g, J, (const double2*)Rr.p, Pold, Pnew, (double2*)Q.p, ctx->d_dinv, shd,
-                                 shd + TEM_MAX_SHIFTS, partials, ctx->d_counters + 5, cst.p, st);
-        tem::launch_cocg_update(ctx->g, J, (double2*)Mu.p, (double2*)Rr.p, Pnew, (const double2*)Q.p, partials,
-                                ctx->d_counters + 6, cst.p, st);
-      }
-      e = hipGetLastError();
-      if (e == hipSuccess) e = hipMemcpyAsync(hs.get(), cst.p, sizeof(tem::CocgState), hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
-      if (e != hipSuccess) break;
-      S.iterations = it;
-      if (hs->breakdown) {
-        cleanup();
-        return fail(ctx, TEM_EBREAKDOWN, "COCG breakdown in the adjoint solves");
-      }
-      if (hs->n_active == 0) break;
+    int its = 0;
+    const int r3 = cocg_solve(ctx, J, (const double2*)H.p, (double2*)Mu.p, (double2*)Rr.p, P0, P1, (double2*)Q.p,
+                              o.rtol, o.max_iter, *hs, its);
+    if (r3 == TEM_ENOCONV) {
+      S.converged = 0;
+    } else if (r3 != TEM_OK) {
+      cleanup();
+      return r3;
     }
-    if (e != hipSuccess) break;
-    if (hs->n_active > 0) S.converged = 0;
+    S.iterations = its;
     for (int j = 0; j < J; ++j) {
       S.iters_per_shift[j] = hs->iters[j];
       S.est_res[j] = hs->hn2[j] > 0 ? std::sqrt(hs->rn2[j] / hs->hn2[j]) : 0.0;
@@ -776,7 +919,8 @@ void tem_destroy(tem_ctx* ctx) {
   if (ctx->d_state) hipFree(ctx->d_state);
   if (ctx->d_counters) hipFree(ctx->d_counters);
   for (DevBuf* b : {&ctx->R, &ctx->pbuf, &ctx->q, &ctx->gvec, &ctx->gc, &ctx->f, &ctx->P, &ctx->C, &ctx->rx,
-                    &ctx->data, &ctx->res, &ctx->cpart, &ctx->sh})
+                    &ctx->data, &ctx->res, &ctx->cpart, &ctx->sh, &ctx->y32, &ctx->refine, &ctx->cst,
+                    &ctx->cocg_part})
     release(*b);
   for (DevBuf& b : ctx->Y) release(b);
   if (ctx->head_pinned) hipHostFree(ctx->head_pinned);

@@ -76,6 +76,7 @@ struct CocgState {
   double hn2[kMaxShifts];                          // |rhs|^2
   double rn2[kMaxShifts];                          // |r|^2
   double tol2;                                     // rtol^2 (set by the host)
+  int cap[kMaxShifts];                             // per-shift iteration cap (set by the host)
   int active[kMaxShifts];
   int iters[kMaxShifts];
   int n_active;
@@ -95,12 +96,20 @@ void launch_scale(long long n, const double* a, const double* x, double* y, hipS
 void launch_to_complex(long long n, const double* x, double2* y, hipStream_t s);
 void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, double2* Y, double2* P,
                       int J, Reduce red, SolveState* st, hipStream_t s);
+void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, float2* Y, float2* P,
+                      int J, Reduce red, SolveState* st, hipStream_t s);
 void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold, double* pnew, double* q,
                          const double* dinv, double s0, Reduce red, SolveState* st, int local, hipStream_t s);
 void launch_seed_update(const GridArgs& g, const double* r, const double* q, double* rnext, Reduce red,
                         SolveState* st, int local, hipStream_t s);
 void launch_block_update(const GridArgs& g, const double* R, double2* Y, double2* P, int J, int B,
                          const SolveState* st, hipStream_t s);
+void launch_block_update(const GridArgs& g, const double* R, float2* Y, float2* P, int J, int B,
+                         const SolveState* st, hipStream_t s);
+// J node-padded complex vectors, FP32 storage widened to FP64: sign 0 sets
+// Y_j = X_j for all j; sign +1 / -1 adds / subtracts X_j for the j in mask
+void launch_accumulate(const GridArgs& g, int J, const float2* X, double2* Y, int sign, unsigned long long mask,
+                       hipStream_t s);
 void launch_shift_block(const GridArgs& g, int J, Reduce red, SolveState* st, hipStream_t s);
 void launch_cstencil(const GridArgs& g, const double2* X, long long xstride, const double* dinv,
                      const double* shift_re, const double* shift_im, int nvec, const double2* rhs,
@@ -129,6 +138,14 @@ void launch_cocg_stencil(const GridArgs& g, int J, const double2* Rr, const doub
                          const double* dinv, const double* sre, const double* sim, double* partials,
                          unsigned int* counter, void* st, hipStream_t s);
 void launch_cocg_update(const GridArgs& g, int J, double2* Mu, double2* Rr, const double2* Pn, const double2* Q,
+                        double* partials, unsigned int* counter, void* st, hipStream_t s);
+// the same batched COCG with complex FP32 vector storage (FP64 scalars and dot products)
+void launch_cocg_init(const GridArgs& g, int J, const double2* H, float2* Mu, float2* Rr, float2* Pold,
+                      double* partials, unsigned int* counter, void* st, hipStream_t s);
+void launch_cocg_stencil(const GridArgs& g, int J, const float2* Rr, const float2* Pold, float2* Pnew, float2* Q,
+                         const double* dinv, const double* sre, const double* sim, double* partials,
+                         unsigned int* counter, void* st, hipStream_t s);
+void launch_cocg_update(const GridArgs& g, int J, float2* Mu, float2* Rr, const float2* Pn, const float2* Q,
                         double* partials, unsigned int* counter, void* st, hipStream_t s);
 void launch_grad_edges(const GridArgs& g, int J, const double2* Mu, const double2* Y, const double* dinv,
                        const double* sre, const double* sim, double* z, hipStream_t s);

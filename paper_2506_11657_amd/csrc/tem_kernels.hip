@@ -32,6 +32,25 @@ __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
   double r = b.re / b.im, den = b.re * r + b.im;
   return {(a.re * r + a.im) / den, (a.im * r - a.re) / den};
 }
+// Complex vectors are stored as double2 (FP64 path) or float2 (complex FP32
+// storage of precision 1); arithmetic is always in double.
+__device__ __forceinline__ cplx ldv(const double2* p, long long i) {
+  const double2 v = p[i];
+  return {v.x, v.y};
+}
+__device__ __forceinline__ cplx ldv(const float2* p, long long i) {
+  const float2 v = p[i];
+  return {(double)v.x, (double)v.y};
+}
+__device__ __forceinline__ void stv(double2* p, long long i, cplx v) { p[i] = make_double2(v.re, v.im); }
+__device__ __forceinline__ void stv(float2* p, long long i, cplx v) {
+  p[i] = make_float2((float)v.re, (float)v.im);
+}
+// the value a store of v into V storage keeps
+__device__ __forceinline__ cplx as_stored(const double2*, cplx v) { return v; }
+__device__ __forceinline__ cplx as_stored(const float2*, cplx v) {
+  return {(double)(float)v.re, (double)(float)v.im};
+}
 __device__ __forceinline__ double zero_of(double) { return 0.0; }
 __device__ __forceinline__ cplx zero_of(cplx) { return {0.0, 0.0}; }
 
@@ -549,9 +568,9 @@ __global__ void __launch_bounds__(64) k_shift_block(const double* __restrict__ u
 // for every shift updated in the block (coefficients from k_seed_update).
 // Coefficients sit in shared memory, (a, c, e_0.., d_0..) per shift.
 constexpr int BU_T = 256;
-template <int BB>
-__global__ void __launch_bounds__(BU_T) k_block_update(long long n3, const double* __restrict__ R, double2* Y,
-                                                       double2* P, int J, const SolveState* st) {
+template <int BB, typename V>
+__global__ void __launch_bounds__(BU_T) k_block_update(long long n3, const double* __restrict__ R, V* Y, V* P, int J,
+                                                       const SolveState* st) {
   extern __shared__ double cf[];
   __shared__ int app[kMaxShifts];
   constexpr int W = 2 * BB + 2;
@@ -574,12 +593,12 @@ __global__ void __launch_bounds__(BU_T) k_block_update(long long n3, const doubl
     for (int j = 0; j < J; ++j) {
       if (!app[j]) continue;
       const double* c = cf + 2 * j * W;
-      const double2 p = P[(long long)j * n3 + e];
-      const double2 y = Y[(long long)j * n3 + e];
-      double pr = c[0] * p.x - c[1] * p.y;
-      double pi = c[0] * p.y + c[1] * p.x;
-      double yr = y.x + c[2] * p.x - c[3] * p.y;
-      double yi = y.y + c[2] * p.y + c[3] * p.x;
+      const cplx p = ldv(P, (long long)j * n3 + e);
+      const cplx y = ldv(Y, (long long)j * n3 + e);
+      double pr = c[0] * p.re - c[1] * p.im;
+      double pi = c[0] * p.im + c[1] * p.re;
+      double yr = y.re + c[2] * p.re - c[3] * p.im;
+      double yi = y.im + c[2] * p.im + c[3] * p.re;
 #pragma unroll
       for (int l = 0; l < BB; ++l) {
         pr += c[4 + 2 * l] * rl[l];
@@ -587,14 +606,15 @@ __global__ void __launch_bounds__(BU_T) k_block_update(long long n3, const doubl
         yr += c[4 + 2 * BB + 2 * l] * rl[l];
         yi += c[5 + 2 * BB + 2 * l] * rl[l];
       }
-      P[(long long)j * n3 + e] = make_double2(pr, pi);
-      Y[(long long)j * n3 + e] = make_double2(yr, yi);
+      stv(P, (long long)j * n3 + e, cplx{pr, pi});
+      stv(Y, (long long)j * n3 + e, cplx{yr, yi});
     }
   }
 }
 
+template <typename V>
 __global__ void __launch_bounds__(UPD_T) k_seed_init(long long n3, const double* __restrict__ gv, double* r0,
-                                                     double* pold, double2* Y, double2* P, int J,
+                                                     double* pold, V* Y, V* P, int J,
                                                      double* __restrict__ partials, SolveState* st) {
   __shared__ double red[8];
   double acc = 0.0;
@@ -603,8 +623,8 @@ __global__ void __launch_bounds__(UPD_T) k_seed_init(long long n3, const double*
     r0[e] = v;
     pold[e] = 0.0;
     for (int j = 0; j < J; ++j) {
-      Y[(long long)j * n3 + e] = make_double2(0.0, 0.0);
-      P[(long long)j * n3 + e] = make_double2(v, 0.0);
+      stv(Y, (long long)j * n3 + e, cplx{0.0, 0.0});
+      stv(P, (long long)j * n3 + e, cplx{v, 0.0});
     }
     acc += v * v;
   }
@@ -864,8 +884,9 @@ __global__ void k_adj_rhs(GridArgs g, int J, int n_rx, const int* __restrict__ r
 
 
 // init: mu = 0, r = h, p_old = 0; rho = r^T r, |h|^2 (partials per shift)
-__global__ void k_cocg_init(long long n3, int J, const double2* __restrict__ H, double2* Mu, double2* Rr,
-                            double2* Pold, double* partials, unsigned int* counter, CocgState* st) {
+template <typename V>
+__global__ void k_cocg_init(long long n3, int J, const double2* __restrict__ H, V* Mu, V* Rr, V* Pold,
+                            double* partials, unsigned int* counter, CocgState* st) {
   __shared__ double red[8];
   __shared__ int flag;
   const int j = blockIdx.y;
@@ -873,10 +894,11 @@ __global__ void k_cocg_init(long long n3, int J, const double2* __restrict__ H, 
   double a_re = 0.0, a_im = 0.0, a_n = 0.0;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n3; e += (long long)nbx * blockDim.x) {
     const long long o = (long long)j * n3 + e;
-    const double2 h = H[o];
-    Mu[o] = make_double2(0.0, 0.0);
-    Rr[o] = h;
-    Pold[o] = make_double2(0.0, 0.0);
+    const cplx hv = as_stored(Rr, ldv(H, o));  // the residual as stored (rounded for FP32 storage)
+    stv(Rr, o, hv);
+    const double2 h = make_double2(hv.re, hv.im);
+    stv(Mu, o, cplx{0.0, 0.0});
+    stv(Pold, o, cplx{0.0, 0.0});
     a_re += h.x * h.x - h.y * h.y;
     a_im += 2.0 * h.x * h.y;
     a_n += h.x * h.x + h.y * h.y;
@@ -918,9 +940,10 @@ __global__ void k_cocg_init(long long n3, int J, const double2* __restrict__ H, 
 }
 
 // p_j = r_j + beta_j p_j ; q_j = (A + s_j) p_j ; partial p^T q per (shift, block)
-__global__ void __launch_bounds__(CTX* CTY) k_cocg_stencil(GridArgs g, const double2* __restrict__ Rr,
-                                                           const double2* __restrict__ Pold, double2* Pnew,
-                                                           double2* Q, const double* __restrict__ dinv,
+template <typename V>
+__global__ void __launch_bounds__(CTX* CTY) k_cocg_stencil(GridArgs g, const V* __restrict__ Rr,
+                                                           const V* __restrict__ Pold, V* Pnew,
+                                                           V* Q, const double* __restrict__ dinv,
                                                            const double* sre, const double* sim, int zblocks,
                                                            double* partials, unsigned int* counter, CocgState* st) {
   __shared__ double red[16];
@@ -934,15 +957,15 @@ __global__ void __launch_bounds__(CTX* CTY) k_cocg_stencil(GridArgs g, const dou
   double d_re = 0.0, d_im = 0.0;
   if (act) {
     auto load = [&](long long v, int c) {
-      const double2 r = Rr[off + c * g.nn + v], p = Pold[off + c * g.nn + v];
-      return cplx{r.x + beta.re * p.x - beta.im * p.y, r.y + beta.re * p.y + beta.im * p.x};
+      const cplx r = ldv(Rr, off + c * g.nn + v), p = ldv(Pold, off + c * g.nn + v);
+      return cplx{r.re + beta.re * p.re - beta.im * p.im, r.im + beta.re * p.im + beta.im * p.re};
     };
     auto emit = [&](long long v, int c, cplx kp, cplx u, double d) {
       const long long e = c * g.nn + v;
       cplx out{0.0, 0.0};
       if (d != 0.0) out = cplx{d * kp.re + shr * u.re - shi * u.im, d * kp.im + shr * u.im + shi * u.re};
-      Pnew[off + e] = make_double2(u.re, u.im);
-      Q[off + e] = make_double2(out.re, out.im);
+      stv(Pnew, off + e, u);
+      stv(Q, off + e, out);
       d_re += u.re * out.re - u.im * out.im;
       d_im += u.re * out.im + u.im * out.re;
     };
@@ -980,9 +1003,9 @@ __global__ void __launch_bounds__(CTX* CTY) k_cocg_stencil(GridArgs g, const dou
 }
 
 // mu_j += alpha_j p_j ; r_j -= alpha_j q_j ; rho_j' = r^T r ; |r|^2 ; beta_j = rho'/rho
-__global__ void k_cocg_update(long long n3, int J, double2* Mu, double2* Rr, const double2* __restrict__ Pn,
-                              const double2* __restrict__ Q, double* partials, unsigned int* counter,
-                              CocgState* st) {
+template <typename V>
+__global__ void k_cocg_update(long long n3, int J, V* Mu, V* Rr, const V* __restrict__ Pn, const V* __restrict__ Q,
+                              double* partials, unsigned int* counter, CocgState* st) {
   __shared__ double red[8];
   __shared__ int flag;
   const int j = blockIdx.y;
@@ -993,14 +1016,17 @@ __global__ void k_cocg_update(long long n3, int J, double2* Mu, double2* Rr, con
   if (act) {
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n3; e += (long long)nbx * blockDim.x) {
       const long long o = (long long)j * n3 + e;
-      const double2 p = Pn[o], q = Q[o];
-      double2 m = Mu[o], r = Rr[o];
-      m.x += al.re * p.x - al.im * p.y;
-      m.y += al.re * p.y + al.im * p.x;
-      r.x -= al.re * q.x - al.im * q.y;
-      r.y -= al.re * q.y + al.im * q.x;
-      Mu[o] = m;
-      Rr[o] = r;
+      const cplx p = ldv(Pn, o), q = ldv(Q, o);
+      cplx m = ldv(Mu, o), rv = ldv(Rr, o);
+      m.re += al.re * p.re - al.im * p.im;
+      m.im += al.re * p.im + al.im * p.re;
+      rv.re -= al.re * q.re - al.im * q.im;
+      rv.im -= al.re * q.im + al.im * q.re;
+      stv(Mu, o, m);
+      // the dot products see the residual as stored
+      const cplx rs = as_stored(Rr, rv);
+      stv(Rr, o, rs);
+      const double2 r = make_double2(rs.re, rs.im);
       a_re += r.x * r.x - r.y * r.y;
       a_im += 2.0 * r.x * r.y;
       a_n += r.x * r.x + r.y * r.y;
@@ -1034,7 +1060,7 @@ __global__ void k_cocg_update(long long n3, int J, double2* Mu, double2* Rr, con
     if (!(isfinite(be.re) && isfinite(be.im) && isfinite(n))) {
       st->breakdown = 1;
       st->active[t] = 0;
-    } else if (n <= st->tol2 * st->hn2[t]) {
+    } else if (n <= st->tol2 * st->hn2[t] || st->iters[t] >= st->cap[t]) {
       st->active[t] = 0;
     }
   }
@@ -1096,6 +1122,29 @@ __global__ void k_caxpy_shifts(long long n3, int J, const double* __restrict__ g
   }
 }
 
+// For J node-padded complex vectors of n3 entries (FP32 storage widened to
+// FP64): sign 0 sets Y_j = X_j for every j; sign +1 / -1 adds / subtracts X_j
+// for the shifts j whose bit is set in mask.
+template <typename V>
+__global__ void k_accumulate(long long n3, int J, const V* __restrict__ X, double2* Y, int sign,
+                             unsigned long long mask) {
+  const long long total = n3 * J;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(e / n3);
+    if (sign != 0 && !((mask >> j) & 1ull)) continue;
+    const cplx x = ldv(X, e);
+    if (sign == 0) {
+      Y[e] = make_double2(x.re, x.im);
+    } else {
+      double2 y = Y[e];
+      y.x += sign * x.re;
+      y.y += sign * x.im;
+      Y[e] = y;
+    }
+  }
+}
+
 int grid_1d(long long n, int threads, int cap) {
   long long b = (n + threads - 1) / threads;
   if (b < 1) b = 1;
@@ -1125,11 +1174,20 @@ void launch_to_complex(long long n, const double* x, double2* y, hipStream_t s) 
   hipLaunchKernelGGL(k_to_complex, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, x, y);
 }
 
+template <typename V>
+static void seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, V* Y, V* P, int J, Reduce red,
+                      SolveState* st, hipStream_t s) {
+  const long long n3 = 3 * g.nn;
+  hipLaunchKernelGGL(k_seed_init<V>, dim3(UPD_BLOCKS), dim3(UPD_T), 0, s, n3, gvec, r0, pold, Y, P, J,
+                     red.partials + kReduceSlots, st);
+}
 void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, double2* Y, double2* P,
                       int J, Reduce red, SolveState* st, hipStream_t s) {
-  const long long n3 = 3 * g.nn;
-  hipLaunchKernelGGL(k_seed_init, dim3(UPD_BLOCKS), dim3(UPD_T), 0, s, n3, gvec, r0, pold, Y, P, J,
-                     red.partials + kReduceSlots, st);
+  seed_init(g, gvec, r0, pold, Y, P, J, red, st, s);
+}
+void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, float2* Y, float2* P,
+                      int J, Reduce red, SolveState* st, hipStream_t s) {
+  seed_init(g, gvec, r0, pold, Y, P, J, red, st, s);
 }
 
 // Seed stencil tile shapes (TX x TY node columns, KZ planes per block); the
@@ -1213,17 +1271,33 @@ void launch_shift_block(const GridArgs& g, int J, Reduce red, SolveState* st, hi
   hipLaunchKernelGGL(k_shift_block, dim3(J), dim3(64), 0, s, (const double*)(red.partials + kReduceSlots), st);
 }
 
-void launch_block_update(const GridArgs& g, const double* R, double2* Y, double2* P, int J, int B,
-                         const SolveState* st, hipStream_t s) {
+template <typename V>
+static void block_update(const GridArgs& g, const double* R, V* Y, V* P, int J, int B, const SolveState* st,
+                         hipStream_t s) {
   const long long n3 = 3 * g.nn;
   const dim3 grid(grid_1d(n3, BU_T, 4096)), block(BU_T);
   const size_t shm = (size_t)J * (2 * B + 2) * 2 * sizeof(double);
   switch (B) {
-    case 16: hipLaunchKernelGGL(k_block_update<16>, grid, block, shm, s, n3, R, Y, P, J, st); break;
-    case 32: hipLaunchKernelGGL(k_block_update<32>, grid, block, shm, s, n3, R, Y, P, J, st); break;
-    case 64: hipLaunchKernelGGL(k_block_update<64>, grid, block, shm, s, n3, R, Y, P, J, st); break;
-    default: hipLaunchKernelGGL(k_block_update<8>, grid, block, shm, s, n3, R, Y, P, J, st); break;
+    case 16: hipLaunchKernelGGL((k_block_update<16, V>), grid, block, shm, s, n3, R, Y, P, J, st); break;
+    case 32: hipLaunchKernelGGL((k_block_update<32, V>), grid, block, shm, s, n3, R, Y, P, J, st); break;
+    case 64: hipLaunchKernelGGL((k_block_update<64, V>), grid, block, shm, s, n3, R, Y, P, J, st); break;
+    default: hipLaunchKernelGGL((k_block_update<8, V>), grid, block, shm, s, n3, R, Y, P, J, st); break;
   }
+}
+void launch_block_update(const GridArgs& g, const double* R, double2* Y, double2* P, int J, int B,
+                         const SolveState* st, hipStream_t s) {
+  block_update(g, R, Y, P, J, B, st, s);
+}
+void launch_block_update(const GridArgs& g, const double* R, float2* Y, float2* P, int J, int B,
+                         const SolveState* st, hipStream_t s) {
+  block_update(g, R, Y, P, J, B, st, s);
+}
+
+void launch_accumulate(const GridArgs& g, int J, const float2* X, double2* Y, int sign, unsigned long long mask,
+                       hipStream_t s) {
+  const long long n3 = 3 * g.nn;
+  hipLaunchKernelGGL(k_accumulate<float2>, dim3(grid_1d(n3 * J, 256, 8192)), dim3(256), 0, s, n3, J, X, Y, sign,
+                     mask);
 }
 
 int cstencil_blocks(const GridArgs& g) {
@@ -1292,27 +1366,56 @@ void launch_adj_rhs(const GridArgs& g, int J, int n_rx, const int* rx, int ks, c
 
 static int cocg_row_blocks(long long n3) { return grid_1d(n3, 256, 128); }
 
-void launch_cocg_init(const GridArgs& g, int J, const double2* H, double2* Mu, double2* Rr, double2* Pold,
-                      double* partials, unsigned int* counter, void* st, hipStream_t s) {
+template <typename V>
+static void cocg_init(const GridArgs& g, int J, const double2* H, V* Mu, V* Rr, V* Pold, double* partials,
+                      unsigned int* counter, void* st, hipStream_t s) {
   const long long n3 = 3 * g.nn;
-  hipLaunchKernelGGL(k_cocg_init, dim3(cocg_row_blocks(n3), J), dim3(256), 0, s, n3, J, H, Mu, Rr, Pold, partials,
+  hipLaunchKernelGGL(k_cocg_init<V>, dim3(cocg_row_blocks(n3), J), dim3(256), 0, s, n3, J, H, Mu, Rr, Pold, partials,
                      counter, (CocgState*)st);
 }
+void launch_cocg_init(const GridArgs& g, int J, const double2* H, double2* Mu, double2* Rr, double2* Pold,
+                      double* partials, unsigned int* counter, void* st, hipStream_t s) {
+  cocg_init(g, J, H, Mu, Rr, Pold, partials, counter, st, s);
+}
+void launch_cocg_init(const GridArgs& g, int J, const double2* H, float2* Mu, float2* Rr, float2* Pold,
+                      double* partials, unsigned int* counter, void* st, hipStream_t s) {
+  cocg_init(g, J, H, Mu, Rr, Pold, partials, counter, st, s);
+}
 
+template <typename V>
+static void cocg_stencil(const GridArgs& g, int J, const V* Rr, const V* Pold, V* Pnew, V* Q, const double* dinv,
+                         const double* sre, const double* sim, double* partials, unsigned int* counter, void* st,
+                         hipStream_t s) {
+  const int zb = (g.nz + CKZ - 1) / CKZ;
+  dim3 grid((g.nx + CTX - 1) / CTX, (g.ny + CTY - 1) / CTY, zb * J);
+  hipLaunchKernelGGL(k_cocg_stencil<V>, grid, dim3(CTX, CTY), 0, s, g, Rr, Pold, Pnew, Q, dinv, sre, sim, zb,
+                     partials, counter, (CocgState*)st);
+}
 void launch_cocg_stencil(const GridArgs& g, int J, const double2* Rr, const double2* Pold, double2* Pnew, double2* Q,
                          const double* dinv, const double* sre, const double* sim, double* partials,
                          unsigned int* counter, void* st, hipStream_t s) {
-  const int zb = (g.nz + CKZ - 1) / CKZ;
-  dim3 grid((g.nx + CTX - 1) / CTX, (g.ny + CTY - 1) / CTY, zb * J);
-  hipLaunchKernelGGL(k_cocg_stencil, grid, dim3(CTX, CTY), 0, s, g, Rr, Pold, Pnew, Q, dinv, sre, sim, zb, partials,
-                     counter, (CocgState*)st);
+  cocg_stencil(g, J, Rr, Pold, Pnew, Q, dinv, sre, sim, partials, counter, st, s);
+}
+void launch_cocg_stencil(const GridArgs& g, int J, const float2* Rr, const float2* Pold, float2* Pnew, float2* Q,
+                         const double* dinv, const double* sre, const double* sim, double* partials,
+                         unsigned int* counter, void* st, hipStream_t s) {
+  cocg_stencil(g, J, Rr, Pold, Pnew, Q, dinv, sre, sim, partials, counter, st, s);
 }
 
+template <typename V>
+static void cocg_update(const GridArgs& g, int J, V* Mu, V* Rr, const V* Pn, const V* Q, double* partials,
+                        unsigned int* counter, void* st, hipStream_t s) {
+  const long long n3 = 3 * g.nn;
+  hipLaunchKernelGGL(k_cocg_update<V>, dim3(cocg_row_blocks(n3), J), dim3(256), 0, s, n3, J, Mu, Rr, Pn, Q, partials,
+                     counter, (CocgState*)st);
+}
 void launch_cocg_update(const GridArgs& g, int J, double2* Mu, double2* Rr, const double2* Pn, const double2* Q,
                         double* partials, unsigned int* counter, void* st, hipStream_t s) {
-  const long long n3 = 3 * g.nn;
-  hipLaunchKernelGGL(k_cocg_update, dim3(cocg_row_blocks(n3), J), dim3(256), 0, s, n3, J, Mu, Rr, Pn, Q, partials,
-                     counter, (CocgState*)st);
+  cocg_update(g, J, Mu, Rr, Pn, Q, partials, counter, st, s);
+}
+void launch_cocg_update(const GridArgs& g, int J, float2* Mu, float2* Rr, const float2* Pn, const float2* Q,
+                        double* partials, unsigned int* counter, void* st, hipStream_t s) {
+  cocg_update(g, J, Mu, Rr, Pn, Q, partials, counter, st, s);
 }
 
 void launch_grad_edges(const GridArgs& g, int J, const double2* Mu, const double2* Y, const double* dinv,

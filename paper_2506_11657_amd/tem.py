@@ -142,6 +142,7 @@ class Context:
         _check(lib().tem_sizes(h, C.byref(ns), C.byref(nu)), h)
         self.n_storage, self.n_unknowns = ns.value, nu.value
         self._n_src = 0
+        self.generation = 0      # counts forward calls and conductivity changes
 
     @classmethod
     def from_workload(cls, wl, device=0, stream=None):
@@ -163,6 +164,7 @@ class Context:
     def set_conductivity(self, sigma, log=False):
         """sigma (nz, ny, nx) S/m (or ln sigma with log=True); numpy or a torch tensor."""
         flags = TEM_SIGMA_LOG if log else 0
+        self.generation += 1
         try:
             import torch
             if isinstance(sigma, torch.Tensor):
@@ -212,6 +214,7 @@ class Context:
         opts = tem_solve_opts(int(precision), float(rtol), int(max_iter), int(block), float(seed_shift),
                               int(refine_max), 1 if keep_solutions else 0, 1 if profile else 0)
         st = tem_stats()
+        self.generation += 1
         status = lib().tem_forward(self._h, src, len(loops), rx, n_rx, T, J, _dptr(xr), _dptr(cr), C.byref(opts),
                                    _dptr(data), fptr, C.byref(st))
         _check(status, self._h, allow=(TEM_ENOCONV,) if allow_noconv else ())

@@ -98,3 +98,26 @@ def test_adjoint_many_receivers_cocg_path(tem):
     err = np.linalg.norm(g.ravel() - g_or) / np.linalg.norm(g_or)
     print("cocg adjoint rel err %.2e" % err)
     assert err <= 1e-8
+
+
+def test_autograd_function_matches_adjoint(tem):
+    """loss.backward() through the autograd Function gives the tem_adjoint
+    gradient; a stale context (another forward in between) raises."""
+    import torch
+    from paper_2506_11657_amd.autograd import receiver_data
+    wl, s, C = _misfit_case(6, 16)
+    ctx = tem.Context.from_workload(wl)
+    rng = np.random.default_rng(5)
+    d_obs = torch.from_numpy(rng.standard_normal((1, 6, len(wl.receivers))) * 1e-9)
+    m = torch.tensor(np.log(wl.sigma), device="cuda", requires_grad=True)
+    d = receiver_data(m, ctx, wl.loops, wl.receivers, -s, C)
+    loss = 0.5 * ((d.cpu() - d_obs) ** 2).sum()
+    loss.backward()
+    d_np, _ = ctx.forward(wl.loops, wl.receivers, -s, C, keep_solutions=True)
+    assert np.array_equal(d_np, d.detach().cpu().numpy())
+    g_ref, _ = ctx.adjoint(d_np - d_obs.numpy())
+    assert np.array_equal(m.grad.cpu().numpy(), g_ref)
+    d2 = receiver_data(m, ctx, wl.loops, wl.receivers, -s, C)
+    ctx.forward(wl.loops, wl.receivers, -s, C)
+    with pytest.raises(RuntimeError):
+        d2.sum().backward()
