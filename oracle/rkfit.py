@@ -42,7 +42,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-HALPHEN = 9.289025491920818  # Halphen's constant H (Sec. 3.4)
+HALPHEN = 9.289025491920818  # Halphen's constant H (Sec. 3.3)
 
 
 def surrogate(tau_min: float, ns: int = 2000) -> np.ndarray:
@@ -242,11 +242,11 @@ def shifts_and_coefficients(fit: dict):
     return -xi, c
 
 
-# -- degree arithmetic of Sec. 3.4 and Table 1 -------------------------------
+# -- degree arithmetic of Sec. 3.3 and Table 1 -------------------------------
 
 def single_time_degree(tol: float) -> int:
     """Smallest m with 2 H^(-m-1/2) <= tol (the asymptotic best-approximation
-    error of exp(-x) of type [m/m], Sec. 3.4)."""
+    error of exp(-x) of type [m/m], Sec. 3.3)."""
     m = 0
     while 2.0 * HALPHEN ** (-m - 0.5) > tol:
         m += 1
@@ -254,7 +254,7 @@ def single_time_degree(tol: float) -> int:
 
 
 def break_even(m_hat: int, m: int) -> float:
-    """K* = ceil(m_hat/2) / ceil(m/2) (Sec. 3.4)."""
+    """K* = ceil(m_hat/2) / ceil(m/2) (Sec. 3.3)."""
     return -(-m_hat // 2) / -(-m // 2)
 
 

@@ -17,7 +17,7 @@ SLOW = os.environ.get("TEM_SLOW") == "1"
 
 def test_table1_first_column_from_halphen():
     """Table 1, ratio 1: the [m/m] degrees 2, 4, 7, 9, 11 follow from the
-    asymptotic best-approximation error 2 H^(-m-1/2) (Sec. 3.4)."""
+    asymptotic best-approximation error 2 H^(-m-1/2) (Sec. 3.3)."""
     got = [R.single_time_degree(tol) for tol in TABLE["tolerances"]]
     assert got == TABLE["degree"]["1"]
 
@@ -93,7 +93,7 @@ def test_time_scaling_invariance():
 @pytest.mark.parametrize("m", [4, 7, 10])
 def test_single_time_near_best(m):
     """One channel: the subdiagonal fit is within a small factor of the best
-    [m/m] approximation error 2 H^(-m-1/2) (Sec. 3.4)."""
+    [m/m] approximation error 2 H^(-m-1/2) (Sec. 3.3)."""
     fit = R.rkfit(np.array([1.0]), m)
     assert fit["err"][0] <= 3.0 * 2.0 * R.HALPHEN ** (-m - 0.5)
 
