@@ -122,7 +122,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="graded64", choices=["graded64", "plain16", "blocky128"])
-    ap.add_argument("--block", type=int, default=32)
+    ap.add_argument("--block", type=int, default=64)
     ap.add_argument("--precision", type=int, default=0, choices=[0, 1],
                     help="1: complex FP32 shift vectors + FP64 residual refinement; the per-channel error "
                          "against an FP64 GPU solve of the same model is reported")

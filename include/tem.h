@@ -78,17 +78,19 @@ typedef struct {
                         stays FP64) and stops at a scaled residual of 1e-6; FP64 residuals
                         rho_j then drive refinement passes, each a batched COCG with complex
                         FP32 vectors on (K + s_j M) d_j = rho_j to a 1e-2 reduction and
-                        x_j += d_j in FP64; a correction that does not lower a shift's FP64
-                        residual is taken back and that shift is not refined again.  On
-                        stiff grids (seed solves of 1e4+ iterations) FP32 Krylov corrections
-                        stagnate and the call returns TEM_ENOCONV with the best iterate.
+                        x_j += omega_j d_j in FP64 with the step omega_j minimizing the FP64
+                        residual, so no pass raises it.  On stiff grids (seed solves of 1e4+
+                        iterations) FP32 Krylov corrections stagnate and the call returns
+                        TEM_ENOCONV with the best iterate.
                         Contraction and receivers are FP64 in both. */
   double rtol;       /* per-shift target in the scaled system y = M^1/2 x, g = M^-1/2 f:
                         precision 0 stops shift j when |zeta_j| ||r||_2 <= rtol ||g||_2
                         (<= 0 selects 1e-12); precision 1 refines until the FP64 residual
-                        ||g - (A + s_j) y_j||_2 <= rtol ||g||_2 (<= 0 selects 1e-8) */
+                        ||g - (A + s_j) y_j||_2 <= rtol ||g||_2 (<= 0 selects 3e-8) */
   int max_iter;      /* cap on seed iterations per solve; <= 0 selects 2000000 */
-  int block;         /* iterations between deferred shift updates (1..64); <= 0 selects 32 */
+  int block;         /* iterations between deferred shift updates (8, 16, 32 or 64; other
+                        values round down, and J (2 block + 2) 16 bytes must fit in 64 KiB);
+                        <= 0 selects 64 */
   double seed_shift; /* real seed shift of the shared recurrence; <= 0 selects
                         max(min_j Re s_j, 1e-3 min_j |s_j|), s_j = -xi_j */
   int refine_max;    /* precision 1: cap on refinement passes; <= 0 selects 8; a shift

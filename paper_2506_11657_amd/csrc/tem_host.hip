@@ -26,7 +26,7 @@ constexpr int kAdjointMultishiftMaxRx = 12;  // adjoint by per-receiver multi-sh
 // drives every shift to the requested rtol (default kRefineTarget), each pass
 // reducing the correction system's residual by kRefinePassTol
 constexpr double kSweepTolFP32 = 1e-6;
-constexpr double kRefineTarget = 1e-8;
+constexpr double kRefineTarget = 3e-8;
 constexpr double kRefinePassTol = 1e-2;
 
 struct DevBuf {
@@ -59,6 +59,7 @@ struct tem_ctx {
   unsigned int* d_counters = nullptr;
   DevBuf R, pbuf, q, gvec, gc, f, P, C, rx, data, res, cpart, sh;
   DevBuf y32, refine, cst, cocg_part;  // precision 1: FP32 shift solutions, refinement COCG vectors and state
+  DevBuf refine64, refdot;             // precision 1: FP64 corrections d_j and (A + s_j) d_j; step lengths
   std::vector<DevBuf> Y;  // per source (kept) or one
   // stored forward state for the adjoint
   bool fwd_valid = false;
@@ -181,7 +182,7 @@ tem_solve_opts resolve_opts(const tem_solve_opts* o) {
   if (o) r = *o;
   if (!(r.rtol > 0.0)) r.rtol = r.precision == 1 ? kRefineTarget : 1e-12;
   if (r.max_iter <= 0) r.max_iter = 2000000;
-  if (r.block <= 0) r.block = 32;
+  if (r.block <= 0) r.block = 64;
   if (r.refine_max <= 0) r.refine_max = 8;
   return r;
 }
@@ -628,10 +629,12 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
     }
     if (o.precision == 1) {
       // FP64 residual refinement: (A + s_j) d_j = rho_j by batched COCG with
-      // complex FP32 vectors to kRefinePassTol, y_j += d_j in FP64, new rho_j.
-      // A correction that does not lower shift j's FP64 residual is taken back
-      // and the shift is not refined further (FP32 Krylov stagnation); the
-      // passes end when no shift is left to refine.
+      // complex FP32 vectors to kRefinePassTol, then the minimal-residual step
+      // y_j += omega_j d_j, omega_j = (w_j, rho_j) / (w_j, w_j), w_j = (A + s_j) d_j
+      // in FP64, so no pass raises a shift's FP64 residual.  Each shift starts
+      // with a COCG budget of twice the sweep's iterations; a shift whose
+      // residual falls by less than 10% gets half its budget next pass and is no
+      // longer refined once that budget is below 32 iterations.
       auto rel = [&](int j) { return std::sqrt(true2[j] / hs.rr0); };
       auto worst = [&]() {
         double w = 0.0;
@@ -639,8 +642,8 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
         return w;
       };
       std::vector<char> stalled(J, 0);
-      // per-shift COCG iteration budget, quartered when a pass is taken back
-      std::vector<int> caps(J, std::min(o.max_iter, std::max(hs.k, 256)));
+      std::vector<int> caps(J, std::min(o.max_iter, 2 * std::max(hs.k, 256)));
+      const int nbd = tem::dot_shifts_blocks(ctx->g);
       int passes = 0;
       while (passes < o.refine_max) {
         unsigned long long todo = 0;
@@ -648,7 +651,10 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
           if (!stalled[j] && rel(j) > o.rtol) todo |= 1ull << j;
         if (!todo) break;
         const size_t vn = (size_t)J * ctx->n3;
-        if ((rc = ensure(ctx, ctx->refine, 5 * vn * sizeof(float2)))) return rc;
+        if ((rc = ensure(ctx, ctx->refine, 5 * vn * sizeof(float2))) ||
+            (rc = ensure(ctx, ctx->refine64, 2 * vn * sizeof(double2))) ||
+            (rc = ensure(ctx, ctx->refdot, (size_t)(3 * nbd + 8) * TEM_MAX_SHIFTS * sizeof(double))))
+          return rc;
         for (int j = 0; j < J; ++j)  // a zero right-hand side leaves shift j inactive (d_j = 0)
           if (!((todo >> j) & 1ull))
             HIPCHK(ctx, hipMemsetAsync((double2*)ctx->P.p + (size_t)j * ctx->n3, 0, ctx->n3 * sizeof(double2), st));
@@ -660,24 +666,43 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
                             kRefinePassTol, cap, cs, its, caps.data());
         if (r2 != TEM_OK && r2 != TEM_ENOCONV) return r2;
         for (int j = 0; j < J; ++j) S.unknown_updates += (double)ctx->nunk * cs.iters[j];
+        // d_j in FP64, w_j = (A + s_j) d_j, dots against rho_j (the P buffer)
+        double2* D = (double2*)ctx->refine64.p;
+        double2* Wv = D + vn;
+        double* dp = (double*)ctx->refdot.p;            // partials, 3 J rows of nbd
+        double* dsum = dp + (size_t)3 * nbd * TEM_MAX_SHIFTS;  // 3 J sums
+        double* om = dsum + 3 * TEM_MAX_SHIFTS;        // 2 J step lengths
+        tem::launch_accumulate(ctx->g, J, v, D, 0, 0, st);
+        tem::launch_cstencil(ctx->g, D, ctx->n3, ctx->d_dinv, shd, shd + TEM_MAX_SHIFTS, J, nullptr, Wv, ctx->n3,
+                             nullptr, st);
+        tem::launch_dot_shifts(ctx->g, J, Wv, (const double2*)ctx->P.p, dp, st);
+        tem::launch_reduce_rows(dp, 3 * J, nbd, dsum, st);
+        HIPCHK(ctx, hipGetLastError());
+        std::vector<double> dots(3 * J), omega(2 * J, 0.0);
+        HIPCHK(ctx, hipMemcpyAsync(dots.data(), dsum, 3 * J * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+        for (int j = 0; j < J; ++j) {
+          const double ww = dots[3 * j + 2];
+          if (((todo >> j) & 1ull) && ww > 0.0 && std::isfinite(ww)) {
+            omega[2 * j] = dots[3 * j] / ww;
+            omega[2 * j + 1] = dots[3 * j + 1] / ww;
+          }
+        }
+        HIPCHK(ctx, hipMemcpyAsync(om, omega.data(), 2 * J * sizeof(double), hipMemcpyHostToDevice, st));
+        tem::launch_caxpy_shifts(ctx->g, J, om, D, Y, st);
         const std::vector<double> before = true2;
-        tem::launch_accumulate(ctx->g, J, v, Y, +1, todo, st);
         ++passes;
         if ((rc = true_residuals())) return rc;
-        unsigned long long back = 0;
+        int slow = 0;
         for (int j = 0; j < J; ++j)
-          if (((todo >> j) & 1ull) && !(true2[j] < before[j])) {
-            back |= 1ull << j;
-            caps[j] /= 4;
+          if (((todo >> j) & 1ull) && !(true2[j] < 0.81 * before[j])) {
+            ++slow;
+            caps[j] /= 2;
             if (caps[j] < 32) stalled[j] = 1;
           }
-        if (back) {
-          tem::launch_accumulate(ctx->g, J, v, Y, -1, back, st);
-          if ((rc = true_residuals())) return rc;
-        }
         if (verbose())
-          fprintf(stderr, "[tem] refinement pass %d: %d COCG iterations, %d shifts taken back, max scaled FP64 "
-                  "residual %.2e\n", passes, its, __builtin_popcountll(back), worst());
+          fprintf(stderr, "[tem] refinement pass %d: %d COCG iterations, %d shifts reduced by < 10%%, max scaled "
+                  "FP64 residual %.2e\n", passes, its, slow, worst());
       }
       S.refine_passes = std::max(S.refine_passes, passes);
       if (worst() > o.rtol) {
@@ -920,7 +945,7 @@ void tem_destroy(tem_ctx* ctx) {
   if (ctx->d_counters) hipFree(ctx->d_counters);
   for (DevBuf* b : {&ctx->R, &ctx->pbuf, &ctx->q, &ctx->gvec, &ctx->gc, &ctx->f, &ctx->P, &ctx->C, &ctx->rx,
                     &ctx->data, &ctx->res, &ctx->cpart, &ctx->sh, &ctx->y32, &ctx->refine, &ctx->cst,
-                    &ctx->cocg_part})
+                    &ctx->cocg_part, &ctx->refine64, &ctx->refdot})
     release(*b);
   for (DevBuf& b : ctx->Y) release(b);
   if (ctx->head_pinned) hipHostFree(ctx->head_pinned);

@@ -152,6 +152,10 @@ void launch_grad_edges(const GridArgs& g, int J, const double2* Mu, const double
 void launch_grad_cells(const GridArgs& g, const double* sigma, const double* z, double* grad, hipStream_t s);
 void launch_caxpy_shifts(const GridArgs& g, int J, const double* gamma, const double2* Yr, double2* Mu,
                          hipStream_t s);
+// per shift (w_j, rho_j) (Hermitian, re and im) and (w_j, w_j): partial sums at
+// partials[(3 j + m) * dot_shifts_blocks(g) + block], m = 0, 1, 2
+int dot_shifts_blocks(const GridArgs& g);
+void launch_dot_shifts(const GridArgs& g, int J, const double2* W, const double2* Rh, double* partials, hipStream_t s);
 
 // ---- host RKFIT (tem_rkfit.cpp) --------------------------------------------
 struct RkfitResult {

@@ -269,12 +269,23 @@ __device__ void stencil_tile(const GridArgs& g, const double* __restrict__ dinv,
 // registers in the same burst.
 // own(c, kz) -> (u, d) is supplied through load(v, c) and dinv.
 // ---------------------------------------------------------------------------
-template <int TX, int TY, int KZ, typename LoadFn, typename EmitFn>
-__device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ dinv, int zb, LoadFn load, EmitFn emit) {
+// Block-3-D stencil tile: all KZ + 2 node planes of a TX x TY tile plus a
+// one-node halo are staged at once.  The raw inputs of every staged value are
+// fetched into registers first (fetch(v, c) returns them); the caller's pre()
+// then runs while those loads are in flight (typically the reduction of the
+// previous kernel's partials that yields the recurrence scalars); finally
+// combine(raw) forms the value, which is scaled by M^-1/2 into LDS.  The face
+// fluxes of KZ + 1 planes are formed in LDS from the 1-D width products, and
+// emit(v, c, (K p')_c, u, M^-1/2) receives every owned edge.
+template <int TX, int TY, int KZ, typename FetchFn, typename PreFn, typename CombineFn, typename EmitFn>
+__device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ dinv, int zb, FetchFn fetch, PreFn pre,
+                                CombineFn combine, EmitFn emit) {
   constexpr int NP = KZ + 2;                                // planes loaded
   constexpr int NE = (TX + 2) * (TY + 2);                   // entries per plane
   constexpr int NT = TX * TY;
   constexpr int NF = (TX + 1) * (TY + 1);                   // flux entries per plane
+  constexpr int NL = (NP * NE + NT - 1) / NT;               // staged entries per thread
+  using Raw = decltype(fetch(0LL, 0));
   __shared__ double sp[NP][3][TY + 2][TX + 2];
   __shared__ double phi[KZ + 1][3][TY + 1][TX + 1];
   // 1-D weights of the block's flux nodes: x (li = 0..TX), y (lj = 0..TY), z (pl = 0..KZ)
@@ -287,8 +298,9 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
   const int k0 = zb * KZ;
   const int i = i0 + tx, j = j0 + ty;
   const bool own = (i < g.nx) && (j < g.ny);
-  // own values (registers)
-  double ou[KZ][3], od[KZ][3];
+  // 1. issue every load: own raw values, staged raw values and M^-1/2, weights
+  Raw ou[KZ][3];
+  double od[KZ][3];
 #pragma unroll
   for (int z = 0; z < KZ; ++z) {
     const int kk = k0 + z;
@@ -297,7 +309,23 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       od[z][c] = ok ? dinv[c * g.nn + v] : 0.0;
-      ou[z][c] = ok ? load(v, c) : 0.0;
+      ou[z][c] = ok ? fetch(v, c) : Raw{};
+    }
+  }
+  Raw hr[NL][3];
+  double hd[NL][3];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    const int e = tid + l * NT;
+    const int pl = e / NE, r = e % NE;
+    const int li = r % (TX + 2), lj = r / (TX + 2);
+    const int gi = i0 - 1 + li, gj = j0 - 1 + lj, kk = k0 - 1 + pl;
+    const bool in = e < NP * NE && gi >= 0 && gi < g.px && gj >= 0 && gj < g.py && kk >= 0 && kk < g.pz;
+    const long long v = in ? node_of(g, gi, gj, kk) : 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      hd[l][c] = in ? dinv[c * g.nn + v] : 0.0;
+      hr[l][c] = in ? fetch(v, c) : Raw{};
     }
   }
   for (int e = tid; e < (TX + 1) + (TY + 1) + (KZ + 1); e += NT) {
@@ -321,18 +349,18 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
       wzd[q] = ok ? g.dw[2][kk] : 0.0;
     }
   }
-  // tile + halo of all planes
-  for (int e = tid; e < NP * NE; e += NT) {
-    const int pl = e / NE, r = e % NE;
-    const int li = r % (TX + 2), lj = r / (TX + 2);
-    const int gi = i0 - 1 + li, gj = j0 - 1 + lj, kk = k0 - 1 + pl;
-    const bool in = gi >= 0 && gi < g.px && gj >= 0 && gj < g.py && kk >= 0 && kk < g.pz;
-    const long long v = in ? node_of(g, gi, gj, kk) : 0;
-    double val[3];
+  // 2. the caller's reduction overlaps the loads above
+  pre();
+  // 3. staged values into LDS
 #pragma unroll
-    for (int c = 0; c < 3; ++c) val[c] = in ? dinv[c * g.nn + v] * load(v, c) : 0.0;
+  for (int l = 0; l < NL; ++l) {
+    const int e = tid + l * NT;
+    if (e < NP * NE) {
+      const int pl = e / NE, r = e % NE;
+      const int li = r % (TX + 2), lj = r / (TX + 2);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) sp[pl][c][lj][li] = val[c];
+      for (int c = 0; c < 3; ++c) sp[pl][c][lj][li] = hd[l][c] * combine(hr[l][c]);
+    }
   }
   __syncthreads();
   // fluxes of planes k0-1 .. k0+KZ-1 (plane index pl: kk = k0 - 1 + pl)
@@ -376,8 +404,9 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
 }
 
 constexpr int STX = 32, STY = 4, SKZ = 2;
-constexpr int UPD_T = 256;
+constexpr int UPD_T = 1024;      // threads per block of the seed update and init
 constexpr int UPD_BLOCKS = 256;  // blocks of the seed update (= partials it leaves)
+constexpr int UPD_PF = 4;        // elements per thread loaded ahead of the update's reduction
 
 // Fixed-order sum of n partials written by the previous kernel (every block
 // of the reading kernel computes the same value; no inter-block traffic).
@@ -400,32 +429,37 @@ __device__ double sum_prev(const double* __restrict__ partials, int n, double* l
 // block and the next kernel sums them in a fixed order, so results are
 // bitwise repeatable and no device-scope fences are needed.
 // ---------------------------------------------------------------------------
+// 4 waves per SIMD keeps two 512-thread tiles resident per CU (the LDS of
+// two tiles fits); the staged registers must then fit in 128 VGPRs
 template <int TX, int TY, int KZ, bool B3D>
-__global__ void __launch_bounds__(TX* TY) k_seed_stencil(GridArgs g, const double* __restrict__ r,
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(4))) k_seed_stencil(GridArgs g, const double* __restrict__ r,
                                                           const double* __restrict__ pold,
                                                           double* __restrict__ pnew, double* __restrict__ q,
                                                           const double* __restrict__ dinv, double s0,
                                                           const double* __restrict__ upd_partials,
                                                           double* __restrict__ partials, SolveState* st, int local) {
   __shared__ double red[16];
-  const double rr = sum_prev(upd_partials, UPD_BLOCKS, red);
-  const double rr_prev = st->rrk[(local + 1) & 1];
-  const double beta = rr / rr_prev;  // rr_{-1} = inf gives beta_{-1} = 0
   const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-  if (bid == 0 && flat_tid() == 0) {
-    if (isinf(rr_prev)) {  // first iteration: rr_0 = (g, g) scales the stopping tolerance
-      st->rr0 = rr;
-      st->tol2 *= rr;
+  double beta = 0.0;
+  // rr_k from the update's partials, beta_{k-1} = rr_k / rr_{k-1} (rr_{-1} = inf gives 0)
+  auto pre = [&]() {
+    const double rr = sum_prev(upd_partials, UPD_BLOCKS, red);
+    const double rr_prev = st->rrk[(local + 1) & 1];
+    beta = rr / rr_prev;
+    if (bid == 0 && flat_tid() == 0) {
+      if (isinf(rr_prev)) {  // first iteration: rr_0 = (g, g) scales the stopping tolerance
+        st->rr0 = rr;
+        st->tol2 *= rr;
+      }
+      st->rrk[local & 1] = rr;
+      const int B = st->B;
+      const int prev = (local + B - 1) % B;  // the step k-1
+      st->beta_h[prev] = beta;
+      st->rr_h[prev] = rr;
+      if (!isfinite(rr)) st->breakdown = 1;
     }
-    st->rrk[local & 1] = rr;
-    const int B = st->B;
-    const int prev = (local + B - 1) % B;  // the step k-1
-    st->beta_h[prev] = beta;
-    st->rr_h[prev] = rr;
-    if (!isfinite(rr)) st->breakdown = 1;
-  }
+  };
   double dot = 0.0;
-  auto load = [&](long long v, int c) { return r[c * g.nn + v] + beta * pold[c * g.nn + v]; };
   auto emit = [&](long long v, int c, double kp, double u, double d) {
     const long long e = c * g.nn + v;
     const double out = d * kp + s0 * u;
@@ -433,8 +467,19 @@ __global__ void __launch_bounds__(TX* TY) k_seed_stencil(GridArgs g, const doubl
     q[e] = out;
     dot += u * out;
   };
-  if constexpr (B3D) stencil_block3d<TX, TY, KZ>(g, dinv, blockIdx.z, load, emit);
-  else stencil_tile<double, TX, TY, KZ>(g, dinv, blockIdx.z, load, emit);
+  if constexpr (B3D) {
+    struct RP {
+      double r, p;
+    };
+    auto fetch = [&](long long v, int c) { return RP{r[c * g.nn + v], pold[c * g.nn + v]}; };
+    auto combine = [&](const RP& x) { return x.r + beta * x.p; };
+    auto emit_raw = [&](long long v, int c, double kp, const RP& x, double d) { emit(v, c, kp, combine(x), d); };
+    stencil_block3d<TX, TY, KZ>(g, dinv, blockIdx.z, fetch, pre, combine, emit_raw);
+  } else {
+    pre();
+    auto load = [&](long long v, int c) { return r[c * g.nn + v] + beta * pold[c * g.nn + v]; };
+    stencil_tile<double, TX, TY, KZ>(g, dinv, blockIdx.z, load, emit);
+  }
   const double s = block_sum(dot, red);
   if (flat_tid() == 0) partials[bid] = s;
 }
@@ -443,11 +488,18 @@ __global__ void __launch_bounds__(UPD_T) k_seed_update(long long n, const double
                                                        const double* __restrict__ q, double* __restrict__ rnext,
                                                        const double* __restrict__ st_partials, int n_st,
                                                        double* __restrict__ partials, SolveState* st, int local) {
-  __shared__ double red[8];
-  // the first grid-stride chunk is loaded before the reduction so that its
-  // latency overlaps the sum of the stencil's partials
+  __shared__ double red[UPD_T / 64];
+  // the first UPD_PF grid-stride elements are loaded before the reduction so
+  // that their latency overlaps the sum of the stencil's partials
+  const long long stride = (long long)gridDim.x * UPD_T;
   const long long e0 = blockIdx.x * (long long)UPD_T + threadIdx.x;
-  const double r0v = e0 < n ? r[e0] : 0.0, q0v = e0 < n ? q[e0] : 0.0;
+  double rv[UPD_PF], qv[UPD_PF];
+#pragma unroll
+  for (int m = 0; m < UPD_PF; ++m) {
+    const long long e = e0 + m * stride;
+    rv[m] = e < n ? r[e] : 0.0;
+    qv[m] = e < n ? q[e] : 0.0;
+  }
   const double pap = sum_prev(st_partials, n_st, red);
   const double rr = st->rrk[local & 1];
   const double alpha = (pap > 0.0 && isfinite(pap)) ? rr / pap : 0.0;
@@ -462,12 +514,16 @@ __global__ void __launch_bounds__(UPD_T) k_seed_update(long long n, const double
     st->pAp = pap;
   }
   double acc = 0.0;
-  if (e0 < n) {
-    const double v = r0v - alpha * q0v;
-    rnext[e0] = v;
-    acc += v * v;
+#pragma unroll
+  for (int m = 0; m < UPD_PF; ++m) {
+    const long long e = e0 + m * stride;
+    if (e < n) {
+      const double v = rv[m] - alpha * qv[m];
+      rnext[e] = v;
+      acc += v * v;
+    }
   }
-  for (long long e = e0 + (long long)gridDim.x * UPD_T; e < n; e += (long long)gridDim.x * UPD_T) {
+  for (long long e = e0 + UPD_PF * stride; e < n; e += stride) {
     const double v = r[e] - alpha * q[e];
     rnext[e] = v;
     acc += v * v;
@@ -616,7 +672,7 @@ template <typename V>
 __global__ void __launch_bounds__(UPD_T) k_seed_init(long long n3, const double* __restrict__ gv, double* r0,
                                                      double* pold, V* Y, V* P, int J,
                                                      double* __restrict__ partials, SolveState* st) {
-  __shared__ double red[8];
+  __shared__ double red[UPD_T / 64];
   double acc = 0.0;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n3; e += (long long)gridDim.x * blockDim.x) {
     const double v = gv[e];
@@ -1145,6 +1201,28 @@ __global__ void k_accumulate(long long n3, int J, const V* __restrict__ X, doubl
   }
 }
 
+// Per shift j: (w_j, rho_j) = sum conj(w) rho (re, im) and (w_j, w_j), as
+// per-block partials at partials[(3 j + m) * gridDim.x + block].
+__global__ void k_dot_shifts(long long n3, const double2* __restrict__ W, const double2* __restrict__ Rh,
+                             double* partials) {
+  __shared__ double red[8];
+  const int j = blockIdx.y;
+  double a_re = 0.0, a_im = 0.0, a_n = 0.0;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n3; e += (long long)gridDim.x * blockDim.x) {
+    const double2 w = W[(long long)j * n3 + e], r = Rh[(long long)j * n3 + e];
+    a_re += w.x * r.x + w.y * r.y;
+    a_im += w.x * r.y - w.y * r.x;
+    a_n += w.x * w.x + w.y * w.y;
+  }
+  const double s_re = block_sum(a_re, red), s_im = block_sum(a_im, red), s_n = block_sum(a_n, red);
+  if (threadIdx.x == 0) {
+    const long long nb = gridDim.x;
+    partials[(3LL * j + 0) * nb + blockIdx.x] = s_re;
+    partials[(3LL * j + 1) * nb + blockIdx.x] = s_im;
+    partials[(3LL * j + 2) * nb + blockIdx.x] = s_n;
+  }
+}
+
 int grid_1d(long long n, int threads, int cap) {
   long long b = (n + threads - 1) / threads;
   if (b < 1) b = 1;
@@ -1270,6 +1348,7 @@ void launch_shift_block(const GridArgs& g, int J, Reduce red, SolveState* st, hi
   (void)g;
   hipLaunchKernelGGL(k_shift_block, dim3(J), dim3(64), 0, s, (const double*)(red.partials + kReduceSlots), st);
 }
+
 
 template <typename V>
 static void block_update(const GridArgs& g, const double* R, V* Y, V* P, int J, int B, const SolveState* st,
@@ -1429,6 +1508,13 @@ void launch_caxpy_shifts(const GridArgs& g, int J, const double* gamma, const do
                          hipStream_t s) {
   const long long n3 = 3 * g.nn;
   hipLaunchKernelGGL(k_caxpy_shifts, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, n3, J, gamma, Yr, Mu);
+}
+
+int dot_shifts_blocks(const GridArgs& g) { return grid_1d(3 * g.nn, 256, 128); }
+
+void launch_dot_shifts(const GridArgs& g, int J, const double2* W, const double2* Rh, double* partials, hipStream_t s) {
+  const long long n3 = 3 * g.nn;
+  hipLaunchKernelGGL(k_dot_shifts, dim3(dot_shifts_blocks(g), J), dim3(256), 0, s, n3, W, Rh, partials);
 }
 
 void launch_grad_cells(const GridArgs& g, const double* sigma, const double* z, double* grad, hipStream_t s) {

@@ -25,7 +25,7 @@ import numpy as np
 from . import tem
 
 
-def footprint_bytes(nx, ny, nz, J, n_src, kind, block=32):
+def footprint_bytes(nx, ny, nz, J, n_src, kind, block=64):
     """Device bytes a request needs: operator arrays, the Krylov workspace of
     one multi-shift solve (residual ring, seed vectors, per-shift x_j and p_j)
     and, for the adjoint, the stored solutions of every source plus the J
