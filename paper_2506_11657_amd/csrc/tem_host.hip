@@ -34,6 +34,21 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Up to this many independent multi-shift solves (loop sources of a forward
+// call, receiver rows of an adjoint) run at once, each on its own stream: the
+// seed kernels of one solve are latency-bound, and concurrent solves fill the
+// device between each other's reduction boundaries.
+constexpr int kMaxConcurrentSolves = 4;
+
+// Workspace of one multi-shift solve.
+struct SolveSlot {
+  DevBuf R, pbuf, q, partials, gvec, P, y32;  // ring, seed p (2), q, partial sums, g, per-shift p_j, FP32 y_j
+  tem::SolveState* d_state = nullptr;
+  void* head = nullptr;          // pinned copy of the solver head
+  hipStream_t stream = nullptr;  // library-owned, default priority
+  hipEvent_t ev = nullptr;       // orders the library stream after this slot
+};
+
 }  // namespace
 
 struct tem_ctx {
@@ -41,7 +56,6 @@ struct tem_ctx {
   hipStream_t stream = nullptr;       // caller's stream (may be the null stream)
   hipStream_t work = nullptr;         // library-owned stream: every kernel runs here
   hipEvent_t order_ev = nullptr;      // orders work after the caller's stream
-  void* head_pinned = nullptr;        // pinned host copy of the solver head
   int nx = 0, ny = 0, nz = 0, ks = 0;
   std::vector<double> hx, hy, hz;
   GridArgs g{};
@@ -54,11 +68,11 @@ struct tem_ctx {
   double* d_sqrtm = nullptr;
   bool has_sigma = false;
   // solver workspace
-  SolveState* d_state = nullptr;
-  double* d_partials = nullptr;
+  std::vector<SolveSlot> slots;
+  hipEvent_t work_ev = nullptr;       // orders the slot streams after the library stream
   unsigned int* d_counters = nullptr;
-  DevBuf R, pbuf, q, gvec, gc, f, P, C, rx, data, res, cpart, sh;
-  DevBuf y32, refine, cst, cocg_part;  // precision 1: FP32 shift solutions, refinement COCG vectors and state
+  DevBuf gc, f, P, C, rx, data, res, cpart, sh;
+  DevBuf refine, cst, cocg_part;       // precision 1: refinement COCG vectors and state
   DevBuf refine64, refdot;             // precision 1: FP64 corrections d_j and (A + s_j) d_j; step lengths
   std::vector<DevBuf> Y;  // per source (kept) or one
   // stored forward state for the adjoint
@@ -194,26 +208,44 @@ int block_length(int requested, int J) {
   return B;
 }
 
-// One multi-shift solve (all J shifts, one right-hand side) on the device.
-// Y receives the scaled solutions y_j = M^{1/2} x_j (node-padded, complex).
-// V = double2 (FP64 path) or float2 (complex FP32 shift vectors, precision 1);
-// P is J node-padded vectors of V, as Y.
+// Create solve slots 0..n-1 (stream, state, pinned head) if they do not exist.
+int ensure_slots(tem_ctx* ctx, int n) {
+  while ((int)ctx->slots.size() < n) {
+    ctx->slots.emplace_back();
+    SolveSlot& sl = ctx->slots.back();
+    HIPCHK(ctx, hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
+    HIPCHK(ctx, hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+    HIPCHK(ctx, hipMalloc(&sl.d_state, sizeof(SolveState)));
+    HIPCHK(ctx, hipHostMalloc(&sl.head, 4096, hipHostMallocDefault));
+  }
+  return TEM_OK;
+}
+
+void release_slot(SolveSlot& sl) {
+  for (DevBuf* b : {&sl.R, &sl.pbuf, &sl.q, &sl.partials, &sl.gvec, &sl.P, &sl.y32}) release(*b);
+  if (sl.d_state) (void)hipFree(sl.d_state);
+  if (sl.head) (void)hipHostFree(sl.head);
+  if (sl.ev) (void)hipEventDestroy(sl.ev);
+  if (sl.stream) (void)hipStreamDestroy(sl.stream);
+}
+
+// njobs independent multi-shift solves (all J shifts each), job i in slot i
+// with its right-hand side g = M^{-1/2} f already in slots[i].gvec (written on
+// the library stream).  Ys[i] receives the scaled solutions y_j = M^{1/2} x_j
+// (node-padded, complex; V = double2 for the FP64 path, float2 for the
+// complex FP32 shift vectors of precision 1); states[i] the final solver state.
+// Each job runs on its slot's stream; the host replays every active job's
+// block graph before it waits for any of them, so their kernels overlap.
 template <typename V>
 int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const std::vector<double>& shifts_im,
-                     double s0, const tem_solve_opts& o, V* Y, V* P, SolveState& host_state, double& seconds) {
+                     double s0, const tem_solve_opts& o, int njobs, V* const* Ys, SolveState* states,
+                     double& seconds) {
   const int J = (int)shifts_re.size();
   const int B = block_length(o.block, J);
-  hipStream_t st = ctx->work;
   const GridArgs& g = ctx->g;
+  const size_t n3 = ctx->n3;
   int rc;
-  (void)st;
-  if ((rc = ensure(ctx, ctx->R, (size_t)B * ctx->n3 * sizeof(double)))) return rc;
-  if ((rc = ensure(ctx, ctx->pbuf, 2 * ctx->n3 * sizeof(double)))) return rc;
-  if ((rc = ensure(ctx, ctx->q, ctx->n3 * sizeof(double)))) return rc;
-  double* R = (double*)ctx->R.p;
-  double* pb = (double*)ctx->pbuf.p;
-  double* q = (double*)ctx->q.p;
-
+  if ((rc = ensure_slots(ctx, njobs))) return rc;
   std::unique_ptr<SolveState> hs(new SolveState());
   std::memset(hs.get(), 0, sizeof(SolveState));
   hs->J = J;
@@ -227,113 +259,167 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     hs->apply[j] = 1;
     hs->a_re[j] = 1.0;
   }
-  HIPCHK(ctx, hipMemcpyAsync(ctx->d_state, hs.get(), sizeof(SolveState), hipMemcpyHostToDevice, st));
-  HIPCHK(ctx, hipMemsetAsync(ctx->d_counters, 0, 16 * sizeof(unsigned int), st));
-  tem::Reduce red{ctx->d_partials, ctx->d_counters};
+  HIPCHK(ctx, hipEventRecord(ctx->work_ev, ctx->work));
   auto t0 = std::chrono::steady_clock::now();
-  tem::launch_seed_init(g, (const double*)ctx->gvec.p, R, pb + ctx->n3, Y, P, J, red, ctx->d_state, st);
-  HIPCHK(ctx, hipGetLastError());
 
-  tem::SolveHead head{};
   // One block of B seed iterations plus the deferred shift update is the same
   // launch sequence every time (slots depend on k mod B only), so it is
-  // captured once into a HIP graph and replayed; with opts.profile the
-  // launches are issued directly with an event pair around each.
-  auto launch_block = [&](bool timed, std::vector<hipEvent_t>& ev) {
-    for (int i = 0; i < B; ++i) {
-      double* r = R + (size_t)i * ctx->n3;
-      double* rn = R + (size_t)((i + 1) % B) * ctx->n3;
-      double* pold = pb + (size_t)((i + 1) & 1) * ctx->n3;
-      double* pnew = pb + (size_t)(i & 1) * ctx->n3;
-      if (timed) (void)hipEventRecord(ev[4 * i], st);
-      tem::launch_seed_stencil(g, r, pold, pnew, q, ctx->d_dinv, s0, red, ctx->d_state, i, st);
-      if (timed) (void)hipEventRecord(ev[4 * i + 1], st);
-      if (timed) (void)hipEventRecord(ev[4 * i + 2], st);
-      tem::launch_seed_update(g, r, q, rn, red, ctx->d_state, i, st);
-      if (timed) (void)hipEventRecord(ev[4 * i + 3], st);
-    }
-    if (timed) (void)hipEventRecord(ev[4 * B], st);
-    tem::launch_shift_block(g, J, red, ctx->d_state, st);
-    tem::launch_block_update(g, R, Y, P, J, B, ctx->d_state, st);
-    if (timed) (void)hipEventRecord(ev[4 * B + 1], st);
-  };
+  // captured once per job into a HIP graph and replayed; with opts.profile,
+  // job 0 issues one block in kProfileEvery directly with an event pair around
+  // each launch (sampling the kernel times inside the timed solve).
+  constexpr int kProfileEvery = 16;
   std::vector<hipEvent_t> ev;
-  hipGraphExec_t exec = nullptr;
-  hipGraph_t graph = nullptr;
   if (o.profile) {
     ev.resize(2 * (2 * B + 1));
     for (auto& e : ev) HIPCHK(ctx, hipEventCreate(&e));
   }
-  // with profiling, one block in kProfileEvery is issued directly with an
-  // event pair around each launch (sampling the kernel times inside the timed
-  // solve); every other block is a replay of the captured graph
-  constexpr int kProfileEvery = 16;
-  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-    launch_block(false, ev);
-    hipError_t ce = hipStreamEndCapture(st, &graph);
-    if (ce == hipSuccess) ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (ce != hipSuccess) {
-      (void)hipGetLastError();
-      if (graph) (void)hipGraphDestroy(graph);
-      graph = nullptr;
-      exec = nullptr;
+  auto launch_block = [&](int i, bool timed) {
+    SolveSlot& sl = ctx->slots[i];
+    hipStream_t st = sl.stream;
+    double* R = (double*)sl.R.p;
+    double* pb = (double*)sl.pbuf.p;
+    double* q = (double*)sl.q.p;
+    const tem::Reduce red{(double*)sl.partials.p, ctx->d_counters};
+    for (int l = 0; l < B; ++l) {
+      double* r = R + (size_t)l * n3;
+      double* rn = R + (size_t)((l + 1) % B) * n3;
+      double* pold = pb + (size_t)((l + 1) & 1) * n3;
+      double* pnew = pb + (size_t)(l & 1) * n3;
+      if (timed) (void)hipEventRecord(ev[4 * l], st);
+      tem::launch_seed_stencil(g, r, pold, pnew, q, ctx->d_dinv, s0, red, sl.d_state, l, st);
+      if (timed) (void)hipEventRecord(ev[4 * l + 1], st);
+      if (timed) (void)hipEventRecord(ev[4 * l + 2], st);
+      tem::launch_seed_update(g, r, q, rn, red, sl.d_state, l, st);
+      if (timed) (void)hipEventRecord(ev[4 * l + 3], st);
     }
-  } else {
-    (void)hipGetLastError();
+    if (timed) (void)hipEventRecord(ev[4 * B], st);
+    tem::launch_shift_block(g, J, red, sl.d_state, st);
+    tem::launch_block_update(g, R, Ys[i], (V*)sl.P.p, J, B, sl.d_state, st);
+    if (timed) (void)hipEventRecord(ev[4 * B + 1], st);
+  };
+  struct Run {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int k = 0;
+    bool done = false;
+  };
+  std::vector<Run> run(njobs);
+  auto cleanup = [&]() {
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    for (Run& r : run) {
+      if (r.exec) (void)hipGraphExecDestroy(r.exec);
+      if (r.graph) (void)hipGraphDestroy(r.graph);
+    }
+  };
+  for (int i = 0; i < njobs; ++i) {
+    SolveSlot& sl = ctx->slots[i];
+    hipStream_t st = sl.stream;
+    if ((rc = ensure(ctx, sl.R, (size_t)B * n3 * sizeof(double))) ||
+        (rc = ensure(ctx, sl.pbuf, 2 * n3 * sizeof(double))) || (rc = ensure(ctx, sl.q, n3 * sizeof(double))) ||
+        (rc = ensure(ctx, sl.P, (size_t)J * n3 * sizeof(double2))) ||
+        (rc = ensure(ctx, sl.partials, 2 * (size_t)tem::kReduceSlots * sizeof(double)))) {
+      cleanup();
+      return rc;
+    }
+    // buffers allocated above are cleared on the library stream; the slot's
+    // work starts after that and after its right-hand side
+    HIPCHK(ctx, hipEventRecord(ctx->work_ev, ctx->work));
+    HIPCHK(ctx, hipStreamWaitEvent(st, ctx->work_ev, 0));
+    HIPCHK(ctx, hipMemcpyAsync(sl.d_state, hs.get(), sizeof(SolveState), hipMemcpyHostToDevice, st));
+    const tem::Reduce red{(double*)sl.partials.p, ctx->d_counters};
+    tem::launch_seed_init(g, (const double*)sl.gvec.p, (double*)sl.R.p, (double*)sl.pbuf.p + n3, Ys[i], (V*)sl.P.p,
+                          J, red, sl.d_state, st);
+    HIPCHK(ctx, hipGetLastError());
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      launch_block(i, false);
+      hipError_t ce = hipStreamEndCapture(st, &run[i].graph);
+      if (ce == hipSuccess) ce = hipGraphInstantiate(&run[i].exec, run[i].graph, nullptr, nullptr, 0);
+      if (ce != hipSuccess) {
+        (void)hipGetLastError();
+        if (run[i].graph) (void)hipGraphDestroy(run[i].graph);
+        run[i].graph = nullptr;
+        run[i].exec = nullptr;
+      }
+    } else {
+      (void)hipGetLastError();
+    }
   }
-  tem::SolveHead* hp = (tem::SolveHead*)ctx->head_pinned;
-  int k = 0;
-  bool done = false;
   hipError_t lerr = hipSuccess;
+  bool breakdown = false;
   int nblock = 0;
   double next_report = 10.0;
-  while (!done && k < o.max_iter) {
+  for (;;) {
+    bool any = false;
     const bool sample = o.profile && (nblock++ % kProfileEvery == 0);
-    if (exec && !sample) lerr = hipGraphLaunch(exec, st);
-    else launch_block(sample, ev);
-    if (lerr == hipSuccess) lerr = hipGetLastError();
-    if (lerr == hipSuccess) lerr = hipMemcpyAsync(hp, ctx->d_state, sizeof(tem::SolveHead), hipMemcpyDeviceToHost, st);
-    if (lerr == hipSuccess) lerr = hipStreamSynchronize(st);
-    if (lerr != hipSuccess) break;
-    k += B;
-    head = *hp;
-    if (sample) {
-      for (int i = 0; i < B; ++i) {
-        float a = 0.f, b = 0.f;
-        (void)hipEventElapsedTime(&a, ev[4 * i], ev[4 * i + 1]);
-        (void)hipEventElapsedTime(&b, ev[4 * i + 2], ev[4 * i + 3]);
-        ctx->prof_ms[TEM_K_STENCIL] += a;
-        ctx->prof_ms[TEM_K_UPDATE] += b;
-      }
-      float c = 0.f;
-      (void)hipEventElapsedTime(&c, ev[4 * B], ev[4 * B + 1]);
-      ctx->prof_ms[TEM_K_BLOCK] += c;
-      ctx->prof_n[TEM_K_STENCIL] += B;
-      ctx->prof_n[TEM_K_UPDATE] += B;
-      ctx->prof_n[TEM_K_BLOCK] += 1;
+    for (int i = 0; i < njobs && lerr == hipSuccess; ++i) {
+      if (run[i].done) continue;
+      any = true;
+      SolveSlot& sl = ctx->slots[i];
+      const bool timed = sample && i == 0;
+      if (run[i].exec && !timed) lerr = hipGraphLaunch(run[i].exec, sl.stream);
+      else launch_block(i, timed);
+      if (lerr == hipSuccess) lerr = hipGetLastError();
+      if (lerr == hipSuccess)
+        lerr = hipMemcpyAsync(sl.head, sl.d_state, sizeof(tem::SolveHead), hipMemcpyDeviceToHost, sl.stream);
     }
-    if (head.breakdown) break;
-    int n_active = 0;
-    for (int j = 0; j < J; ++j) n_active += head.active[j];
-    if (n_active == 0) done = true;
+    if (!any || lerr != hipSuccess) break;
+    int n_active_all = 0;
+    for (int i = 0; i < njobs && lerr == hipSuccess; ++i) {
+      if (run[i].done) continue;
+      SolveSlot& sl = ctx->slots[i];
+      lerr = hipStreamSynchronize(sl.stream);
+      if (lerr != hipSuccess) break;
+      run[i].k += B;
+      const tem::SolveHead head = *(const tem::SolveHead*)sl.head;
+      int n_active = 0;
+      for (int j = 0; j < J; ++j) n_active += head.active[j];
+      n_active_all += n_active;
+      if (head.breakdown) breakdown = true;
+      if (head.breakdown || n_active == 0 || run[i].k >= o.max_iter) run[i].done = true;
+      if (sample && i == 0) {
+        for (int l = 0; l < B; ++l) {
+          float a = 0.f, b = 0.f;
+          (void)hipEventElapsedTime(&a, ev[4 * l], ev[4 * l + 1]);
+          (void)hipEventElapsedTime(&b, ev[4 * l + 2], ev[4 * l + 3]);
+          ctx->prof_ms[TEM_K_STENCIL] += a;
+          ctx->prof_ms[TEM_K_UPDATE] += b;
+        }
+        float c = 0.f;
+        (void)hipEventElapsedTime(&c, ev[4 * B], ev[4 * B + 1]);
+        ctx->prof_ms[TEM_K_BLOCK] += c;
+        ctx->prof_n[TEM_K_STENCIL] += B;
+        ctx->prof_n[TEM_K_UPDATE] += B;
+        ctx->prof_n[TEM_K_BLOCK] += 1;
+      }
+    }
     if (verbose()) {
       const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       if (el >= next_report) {
-        fprintf(stderr, "[tem] multi-shift: %d iterations, %d of %d shifts active, %.1f s\n", k, n_active, J, el);
+        fprintf(stderr, "[tem] multi-shift: %d solves, %d iterations, %d shifts active, %.1f s\n", njobs, run[0].k,
+                n_active_all, el);
         next_report = el + 10.0;
       }
     }
   }
-  for (auto& e : ev) (void)hipEventDestroy(e);
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
-  if (lerr != hipSuccess) return fail(ctx, TEM_EHIP, std::string("solver loop: ") + hipGetErrorString(lerr));
+  if (lerr != hipSuccess) {
+    cleanup();
+    return fail(ctx, TEM_EHIP, std::string("solver loop: ") + hipGetErrorString(lerr));
+  }
   seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  HIPCHK(ctx, hipMemcpyAsync(&host_state, ctx->d_state, sizeof(SolveState), hipMemcpyDeviceToHost, st));
-  HIPCHK(ctx, hipStreamSynchronize(st));
-  if (host_state.breakdown) return fail(ctx, TEM_EBREAKDOWN, "Krylov breakdown in the shared recurrence");
-  for (int j = 0; j < J; ++j)
-    if (host_state.active[j]) return fail(ctx, TEM_ENOCONV, "max_iter reached before every shift converged");
+  for (int i = 0; i < njobs; ++i) {
+    SolveSlot& sl = ctx->slots[i];
+    HIPCHK(ctx, hipMemcpyAsync(&states[i], sl.d_state, sizeof(SolveState), hipMemcpyDeviceToHost, sl.stream));
+    HIPCHK(ctx, hipStreamSynchronize(sl.stream));
+    // later work on the library stream reads Ys[i]
+    HIPCHK(ctx, hipEventRecord(sl.ev, sl.stream));
+    HIPCHK(ctx, hipStreamWaitEvent(ctx->work, sl.ev, 0));
+  }
+  cleanup();
+  for (int i = 0; i < njobs; ++i) breakdown |= states[i].breakdown != 0;
+  if (breakdown) return fail(ctx, TEM_EBREAKDOWN, "Krylov breakdown in the shared recurrence");
+  for (int i = 0; i < njobs; ++i)
+    for (int j = 0; j < J; ++j)
+      if (states[i].active[j]) return fail(ctx, TEM_ENOCONV, "max_iter reached before every shift converged");
   return TEM_OK;
 }
 
@@ -463,13 +549,11 @@ int tem_setup_grid(tem_ctx** out, int nx, int ny, int nz, const double* hx, cons
   HIPCHK(ctx, hipMalloc(&c->d_mass, c->n3 * sizeof(double)));
   HIPCHK(ctx, hipMalloc(&c->d_dinv, c->n3 * sizeof(double)));
   HIPCHK(ctx, hipMalloc(&c->d_sqrtm, c->n3 * sizeof(double)));
-  HIPCHK(ctx, hipMalloc(&c->d_state, sizeof(SolveState)));
-  HIPCHK(ctx, hipMalloc(&c->d_partials, 2 * tem::kReduceSlots * sizeof(double)));
   HIPCHK(ctx, hipMalloc(&c->d_counters, 16 * sizeof(unsigned int)));
   HIPCHK(ctx, hipMemset(c->d_counters, 0, 16 * sizeof(unsigned int)));
   HIPCHK(ctx, hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking));
   HIPCHK(ctx, hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming));
-  HIPCHK(ctx, hipHostMalloc(&c->head_pinned, 4096, hipHostMallocDefault));
+  HIPCHK(ctx, hipEventCreateWithFlags(&c->work_ev, hipEventDisableTiming));
   *out = c.release();
   return TEM_OK;
 }
@@ -541,13 +625,17 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
   if ((rc = order_after_caller(ctx))) return rc;
   hipStream_t st = ctx->work;
   const size_t ysz = (size_t)J * ctx->n3 * sizeof(double2);
-  const int nY = o.keep_solutions ? n_src : 1;
+  const int nconc = std::min(n_src, kMaxConcurrentSolves);  // sources solved at once
+  const int nY = o.keep_solutions ? n_src : nconc;
   if ((int)ctx->Y.size() < nY) ctx->Y.resize(nY);
   for (int s = 0; s < nY; ++s)
     if ((rc = ensure(ctx, ctx->Y[s], ysz))) return rc;
-  if ((rc = ensure(ctx, ctx->gvec, ctx->n3 * sizeof(double)))) return rc;
+  if ((rc = ensure_slots(ctx, nconc))) return rc;
+  for (int i = 0; i < nconc; ++i) {
+    if ((rc = ensure(ctx, ctx->slots[i].gvec, ctx->n3 * sizeof(double)))) return rc;
+    if (o.precision == 1 && (rc = ensure(ctx, ctx->slots[i].y32, (size_t)J * ctx->n3 * sizeof(float2)))) return rc;
+  }
   if ((rc = ensure(ctx, ctx->P, (size_t)J * ctx->n3 * sizeof(double2)))) return rc;
-  if (o.precision == 1 && (rc = ensure(ctx, ctx->y32, (size_t)J * ctx->n3 * sizeof(float2)))) return rc;
   if ((rc = ensure(ctx, ctx->gc, ctx->n3 * sizeof(double2)))) return rc;
   if ((rc = ensure(ctx, ctx->f, ctx->n3 * sizeof(double)))) return rc;
   if ((rc = ensure(ctx, ctx->C, 2 * (size_t)J * T * sizeof(double)))) return rc;
@@ -574,26 +662,36 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
     ctx->prof_n[i] = 0;
   }
   S.converged = 1;
-  std::vector<double> f(ctx->n3);
+  std::vector<std::vector<double>> fs(nconc, std::vector<double>(ctx->n3));
   std::vector<double> true2(J);
+  std::vector<SolveState> states(nconc);
   int status = TEM_OK;
-  for (int s = 0; s < n_src; ++s) {
-    double2* Y = (double2*)ctx->Y[o.keep_solutions ? s : 0].p;
-    loop_source(ctx, src[s], f);
-    HIPCHK(ctx, hipMemcpyAsync(ctx->f.p, f.data(), ctx->n3 * sizeof(double), hipMemcpyHostToDevice, st));
-    tem::launch_scale(ctx->n3, ctx->d_dinv, (const double*)ctx->f.p, (double*)ctx->gvec.p, st);  // g = M^-1/2 f
-    HIPCHK(ctx, hipGetLastError());
-    SolveState hs;
+  for (int s_first = 0; s_first < n_src; s_first += nconc) {
+    const int nb = std::min(nconc, n_src - s_first);
+    // right-hand sides g = M^-1/2 f of this group, one per solve slot
+    for (int i = 0; i < nb; ++i) {
+      loop_source(ctx, src[s_first + i], fs[i]);
+      HIPCHK(ctx, hipMemcpyAsync(ctx->f.p, fs[i].data(), ctx->n3 * sizeof(double), hipMemcpyHostToDevice, st));
+      tem::launch_scale(ctx->n3, ctx->d_dinv, (const double*)ctx->f.p, (double*)ctx->slots[i].gvec.p, st);
+      HIPCHK(ctx, hipGetLastError());
+    }
     double secs = 0.0;
     int r;
     if (o.precision == 1) {
-      // sweep with complex FP32 shift vectors, then y_j widened to FP64
+      // sweeps with complex FP32 shift vectors, then y_j widened to FP64
       tem_solve_opts o32 = o;
       o32.rtol = std::max(o.rtol, kSweepTolFP32);
-      r = multishift_solve(ctx, sre, sim, s0, o32, (float2*)ctx->y32.p, (float2*)ctx->P.p, hs, secs);
-      if (r == TEM_OK || r == TEM_ENOCONV) tem::launch_accumulate(ctx->g, J, (const float2*)ctx->y32.p, Y, 0, 0, st);
+      std::vector<float2*> ys(nb);
+      for (int i = 0; i < nb; ++i) ys[i] = (float2*)ctx->slots[i].y32.p;
+      r = multishift_solve(ctx, sre, sim, s0, o32, nb, ys.data(), states.data(), secs);
+      if (r == TEM_OK || r == TEM_ENOCONV)
+        for (int i = 0; i < nb; ++i)
+          tem::launch_accumulate(ctx->g, J, ys[i], (double2*)ctx->Y[o.keep_solutions ? s_first + i : i].p, 0, 0,
+                                 st);
     } else {
-      r = multishift_solve(ctx, sre, sim, s0, o, Y, (double2*)ctx->P.p, hs, secs);
+      std::vector<double2*> ys(nb);
+      for (int i = 0; i < nb; ++i) ys[i] = (double2*)ctx->Y[o.keep_solutions ? s_first + i : i].p;
+      r = multishift_solve(ctx, sre, sim, s0, o, nb, ys.data(), states.data(), secs);
     }
     if (r == TEM_ENOCONV) {
       S.converged = 0;
@@ -601,130 +699,135 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
     } else if (r != TEM_OK) {
       return r;
     }
-    S.iterations = hs.k;
-    for (int j = 0; j < J; ++j) {
-      S.iters_per_shift[j] = hs.iters[j];
-      S.est_res[j] = hs.est[j] / std::sqrt(hs.rr0);
-      S.unknown_updates += (double)ctx->nunk * hs.iters[j];
-    }
-    // FP64 true residuals rho_j = g - (A + s_j) y_j into the P buffer (free
-    // after the sweep) and ||rho_j||^2 into true2
-    tem::launch_to_complex(ctx->n3, (const double*)ctx->gvec.p, (double2*)ctx->gc.p, st);
-    auto true_residuals = [&]() -> int {
-      tem::launch_cstencil(ctx->g, Y, ctx->n3, ctx->d_dinv, shd, shd + TEM_MAX_SHIFTS, J, (const double2*)ctx->gc.p,
-                           (double2*)ctx->P.p, ctx->n3, (double*)ctx->cpart.p, st);
-      tem::launch_reduce_rows((const double*)ctx->cpart.p, J, cpb, shd + 2 * TEM_MAX_SHIFTS, st);
-      HIPCHK(ctx, hipGetLastError());
-      HIPCHK(ctx, hipMemcpyAsync(true2.data(), shd + 2 * TEM_MAX_SHIFTS, J * sizeof(double), hipMemcpyDeviceToHost,
-                                 st));
-      HIPCHK(ctx, hipStreamSynchronize(st));
-      return TEM_OK;
-    };
-    if ((rc = true_residuals())) return rc;
-    if (verbose()) {
-      double w = 0.0;
-      for (int j = 0; j < J; ++j) w = std::max(w, std::sqrt(true2[j] / hs.rr0));
-      fprintf(stderr, "[tem] source %d: %d seed iterations in %.2f s, max scaled FP64 residual %.2e\n", s, hs.k, secs,
-              w);
-    }
-    if (o.precision == 1) {
-      // FP64 residual refinement: (A + s_j) d_j = rho_j by batched COCG with
-      // complex FP32 vectors to kRefinePassTol, then the minimal-residual step
-      // y_j += omega_j d_j, omega_j = (w_j, rho_j) / (w_j, w_j), w_j = (A + s_j) d_j
-      // in FP64, so no pass raises a shift's FP64 residual.  Each shift starts
-      // with a COCG budget of twice the sweep's iterations; a shift whose
-      // residual falls by less than 10% gets half its budget next pass and is no
-      // longer refined once that budget is below 32 iterations.
-      auto rel = [&](int j) { return std::sqrt(true2[j] / hs.rr0); };
-      auto worst = [&]() {
-        double w = 0.0;
-        for (int j = 0; j < J; ++j) w = std::max(w, rel(j));
-        return w;
-      };
-      std::vector<char> stalled(J, 0);
-      std::vector<int> caps(J, std::min(o.max_iter, 2 * std::max(hs.k, 256)));
-      const int nbd = tem::dot_shifts_blocks(ctx->g);
-      int passes = 0;
-      while (passes < o.refine_max) {
-        unsigned long long todo = 0;
-        for (int j = 0; j < J; ++j)
-          if (!stalled[j] && rel(j) > o.rtol) todo |= 1ull << j;
-        if (!todo) break;
-        const size_t vn = (size_t)J * ctx->n3;
-        if ((rc = ensure(ctx, ctx->refine, 5 * vn * sizeof(float2))) ||
-            (rc = ensure(ctx, ctx->refine64, 2 * vn * sizeof(double2))) ||
-            (rc = ensure(ctx, ctx->refdot, (size_t)(3 * nbd + 8) * TEM_MAX_SHIFTS * sizeof(double))))
-          return rc;
-        for (int j = 0; j < J; ++j)  // a zero right-hand side leaves shift j inactive (d_j = 0)
-          if (!((todo >> j) & 1ull))
-            HIPCHK(ctx, hipMemsetAsync((double2*)ctx->P.p + (size_t)j * ctx->n3, 0, ctx->n3 * sizeof(double2), st));
-        float2* v = (float2*)ctx->refine.p;
-        tem::CocgState cs;
-        int its = 0;
-        const int cap = *std::max_element(caps.begin(), caps.end());
-        int r2 = cocg_solve(ctx, J, (const double2*)ctx->P.p, v, v + vn, v + 2 * vn, v + 3 * vn, v + 4 * vn,
-                            kRefinePassTol, cap, cs, its, caps.data());
-        if (r2 != TEM_OK && r2 != TEM_ENOCONV) return r2;
-        for (int j = 0; j < J; ++j) S.unknown_updates += (double)ctx->nunk * cs.iters[j];
-        // d_j in FP64, w_j = (A + s_j) d_j, dots against rho_j (the P buffer)
-        double2* D = (double2*)ctx->refine64.p;
-        double2* Wv = D + vn;
-        double* dp = (double*)ctx->refdot.p;            // partials, 3 J rows of nbd
-        double* dsum = dp + (size_t)3 * nbd * TEM_MAX_SHIFTS;  // 3 J sums
-        double* om = dsum + 3 * TEM_MAX_SHIFTS;        // 2 J step lengths
-        tem::launch_accumulate(ctx->g, J, v, D, 0, 0, st);
-        tem::launch_cstencil(ctx->g, D, ctx->n3, ctx->d_dinv, shd, shd + TEM_MAX_SHIFTS, J, nullptr, Wv, ctx->n3,
-                             nullptr, st);
-        tem::launch_dot_shifts(ctx->g, J, Wv, (const double2*)ctx->P.p, dp, st);
-        tem::launch_reduce_rows(dp, 3 * J, nbd, dsum, st);
+    for (int i = 0; i < nb; ++i) {
+      const int s = s_first + i;
+      double2* Y = (double2*)ctx->Y[o.keep_solutions ? s : i].p;
+      const SolveState& hs = states[i];
+      S.iterations = hs.k;
+      for (int j = 0; j < J; ++j) {
+        S.iters_per_shift[j] = hs.iters[j];
+        S.est_res[j] = hs.est[j] / std::sqrt(hs.rr0);
+        S.unknown_updates += (double)ctx->nunk * hs.iters[j];
+      }
+      // FP64 true residuals rho_j = g - (A + s_j) y_j into the P buffer (free
+      // after the sweep) and ||rho_j||^2 into true2
+      tem::launch_to_complex(ctx->n3, (const double*)ctx->slots[i].gvec.p, (double2*)ctx->gc.p, st);
+      auto true_residuals = [&]() -> int {
+        tem::launch_cstencil(ctx->g, Y, ctx->n3, ctx->d_dinv, shd, shd + TEM_MAX_SHIFTS, J, (const double2*)ctx->gc.p,
+                             (double2*)ctx->P.p, ctx->n3, (double*)ctx->cpart.p, st);
+        tem::launch_reduce_rows((const double*)ctx->cpart.p, J, cpb, shd + 2 * TEM_MAX_SHIFTS, st);
         HIPCHK(ctx, hipGetLastError());
-        std::vector<double> dots(3 * J), omega(2 * J, 0.0);
-        HIPCHK(ctx, hipMemcpyAsync(dots.data(), dsum, 3 * J * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipMemcpyAsync(true2.data(), shd + 2 * TEM_MAX_SHIFTS, J * sizeof(double), hipMemcpyDeviceToHost,
+                                   st));
         HIPCHK(ctx, hipStreamSynchronize(st));
-        for (int j = 0; j < J; ++j) {
-          const double ww = dots[3 * j + 2];
-          if (((todo >> j) & 1ull) && ww > 0.0 && std::isfinite(ww)) {
-            omega[2 * j] = dots[3 * j] / ww;
-            omega[2 * j + 1] = dots[3 * j + 1] / ww;
+        return TEM_OK;
+      };
+      if ((rc = true_residuals())) return rc;
+      if (verbose()) {
+        double w = 0.0;
+        for (int j = 0; j < J; ++j) w = std::max(w, std::sqrt(true2[j] / hs.rr0));
+        fprintf(stderr, "[tem] source %d: %d seed iterations in %.2f s, max scaled FP64 residual %.2e\n", s, hs.k, secs,
+                w);
+      }
+      if (o.precision == 1) {
+        // FP64 residual refinement: (A + s_j) d_j = rho_j by batched COCG with
+        // complex FP32 vectors to kRefinePassTol, then the minimal-residual step
+        // y_j += omega_j d_j, omega_j = (w_j, rho_j) / (w_j, w_j), w_j = (A + s_j) d_j
+        // in FP64, so no pass raises a shift's FP64 residual.  Each shift starts
+        // with a COCG budget of twice the sweep's iterations; a shift whose
+        // residual falls by less than 10% gets half its budget next pass and is no
+        // longer refined once that budget is below 32 iterations.
+        auto rel = [&](int j) { return std::sqrt(true2[j] / hs.rr0); };
+        auto worst = [&]() {
+          double w = 0.0;
+          for (int j = 0; j < J; ++j) w = std::max(w, rel(j));
+          return w;
+        };
+        std::vector<char> stalled(J, 0);
+        std::vector<int> caps(J, std::min(o.max_iter, 2 * std::max(hs.k, 256)));
+        const int nbd = tem::dot_shifts_blocks(ctx->g);
+        int passes = 0;
+        while (passes < o.refine_max) {
+          unsigned long long todo = 0;
+          for (int j = 0; j < J; ++j)
+            if (!stalled[j] && rel(j) > o.rtol) todo |= 1ull << j;
+          if (!todo) break;
+          const size_t vn = (size_t)J * ctx->n3;
+          if ((rc = ensure(ctx, ctx->refine, 5 * vn * sizeof(float2))) ||
+              (rc = ensure(ctx, ctx->refine64, 2 * vn * sizeof(double2))) ||
+              (rc = ensure(ctx, ctx->refdot, (size_t)(3 * nbd + 8) * TEM_MAX_SHIFTS * sizeof(double))))
+            return rc;
+          for (int j = 0; j < J; ++j)  // a zero right-hand side leaves shift j inactive (d_j = 0)
+            if (!((todo >> j) & 1ull))
+              HIPCHK(ctx, hipMemsetAsync((double2*)ctx->P.p + (size_t)j * ctx->n3, 0, ctx->n3 * sizeof(double2), st));
+          float2* v = (float2*)ctx->refine.p;
+          tem::CocgState cs;
+          int its = 0;
+          const int cap = *std::max_element(caps.begin(), caps.end());
+          int r2 = cocg_solve(ctx, J, (const double2*)ctx->P.p, v, v + vn, v + 2 * vn, v + 3 * vn, v + 4 * vn,
+                              kRefinePassTol, cap, cs, its, caps.data());
+          if (r2 != TEM_OK && r2 != TEM_ENOCONV) return r2;
+          for (int j = 0; j < J; ++j) S.unknown_updates += (double)ctx->nunk * cs.iters[j];
+          // d_j in FP64, w_j = (A + s_j) d_j, dots against rho_j (the P buffer)
+          double2* D = (double2*)ctx->refine64.p;
+          double2* Wv = D + vn;
+          double* dp = (double*)ctx->refdot.p;            // partials, 3 J rows of nbd
+          double* dsum = dp + (size_t)3 * nbd * TEM_MAX_SHIFTS;  // 3 J sums
+          double* om = dsum + 3 * TEM_MAX_SHIFTS;        // 2 J step lengths
+          tem::launch_accumulate(ctx->g, J, v, D, 0, 0, st);
+          tem::launch_cstencil(ctx->g, D, ctx->n3, ctx->d_dinv, shd, shd + TEM_MAX_SHIFTS, J, nullptr, Wv, ctx->n3,
+                               nullptr, st);
+          tem::launch_dot_shifts(ctx->g, J, Wv, (const double2*)ctx->P.p, dp, st);
+          tem::launch_reduce_rows(dp, 3 * J, nbd, dsum, st);
+          HIPCHK(ctx, hipGetLastError());
+          std::vector<double> dots(3 * J), omega(2 * J, 0.0);
+          HIPCHK(ctx, hipMemcpyAsync(dots.data(), dsum, 3 * J * sizeof(double), hipMemcpyDeviceToHost, st));
+          HIPCHK(ctx, hipStreamSynchronize(st));
+          for (int j = 0; j < J; ++j) {
+            const double ww = dots[3 * j + 2];
+            if (((todo >> j) & 1ull) && ww > 0.0 && std::isfinite(ww)) {
+              omega[2 * j] = dots[3 * j] / ww;
+              omega[2 * j + 1] = dots[3 * j + 1] / ww;
+            }
           }
+          HIPCHK(ctx, hipMemcpyAsync(om, omega.data(), 2 * J * sizeof(double), hipMemcpyHostToDevice, st));
+          tem::launch_caxpy_shifts(ctx->g, J, om, D, Y, st);
+          const std::vector<double> before = true2;
+          ++passes;
+          if ((rc = true_residuals())) return rc;
+          int slow = 0;
+          for (int j = 0; j < J; ++j)
+            if (((todo >> j) & 1ull) && !(true2[j] < 0.81 * before[j])) {
+              ++slow;
+              caps[j] /= 2;
+              if (caps[j] < 32) stalled[j] = 1;
+            }
+          if (verbose())
+            fprintf(stderr, "[tem] refinement pass %d: %d COCG iterations, %d shifts reduced by < 10%%, max scaled "
+                    "FP64 residual %.2e\n", passes, its, slow, worst());
         }
-        HIPCHK(ctx, hipMemcpyAsync(om, omega.data(), 2 * J * sizeof(double), hipMemcpyHostToDevice, st));
-        tem::launch_caxpy_shifts(ctx->g, J, om, D, Y, st);
-        const std::vector<double> before = true2;
-        ++passes;
-        if ((rc = true_residuals())) return rc;
-        int slow = 0;
-        for (int j = 0; j < J; ++j)
-          if (((todo >> j) & 1ull) && !(true2[j] < 0.81 * before[j])) {
-            ++slow;
-            caps[j] /= 2;
-            if (caps[j] < 32) stalled[j] = 1;
-          }
-        if (verbose())
-          fprintf(stderr, "[tem] refinement pass %d: %d COCG iterations, %d shifts reduced by < 10%%, max scaled "
-                  "FP64 residual %.2e\n", passes, its, slow, worst());
+        S.refine_passes = std::max(S.refine_passes, passes);
+        if (worst() > o.rtol) {
+          S.converged = 0;
+          status = fail(ctx, TEM_ENOCONV, "FP64 residual refinement did not reach rtol within refine_max passes");
+        }
       }
-      S.refine_passes = std::max(S.refine_passes, passes);
-      if (worst() > o.rtol) {
-        S.converged = 0;
-        status = fail(ctx, TEM_ENOCONV, "FP64 residual refinement did not reach rtol within refine_max passes");
+      // receivers and (optionally) full fields
+      if (n_rx > 0) {
+        tem::launch_receivers(ctx->g, Y, J, ctx->d_dinv, (const double*)ctx->C.p, T, (const int*)ctx->rx.p, n_rx,
+                              ctx->ks, (double*)ctx->data.p, st);
+        HIPCHK(ctx, hipGetLastError());
+        HIPCHK(ctx, hipMemcpyAsync(data + (size_t)s * T * n_rx, ctx->data.p, (size_t)T * n_rx * sizeof(double),
+                                   hipMemcpyDeviceToHost, st));
       }
+      if (fields) {
+        tem::launch_contract(ctx->g, Y, J, ctx->d_dinv, (const double*)ctx->C.p, T,
+                             fields + (size_t)s * T * ctx->nstore, st);
+        HIPCHK(ctx, hipGetLastError());
+      }
+      HIPCHK(ctx, hipStreamSynchronize(st));
+      for (int j = 0; j < J; ++j) S.true_res[j] = std::sqrt(true2[j] / hs.rr0);
     }
-    // receivers and (optionally) full fields
-    if (n_rx > 0) {
-      tem::launch_receivers(ctx->g, Y, J, ctx->d_dinv, (const double*)ctx->C.p, T, (const int*)ctx->rx.p, n_rx,
-                            ctx->ks, (double*)ctx->data.p, st);
-      HIPCHK(ctx, hipGetLastError());
-      HIPCHK(ctx, hipMemcpyAsync(data + (size_t)s * T * n_rx, ctx->data.p, (size_t)T * n_rx * sizeof(double),
-                                 hipMemcpyDeviceToHost, st));
-    }
-    if (fields) {
-      tem::launch_contract(ctx->g, Y, J, ctx->d_dinv, (const double*)ctx->C.p, T,
-                           fields + (size_t)s * T * ctx->nstore, st);
-      HIPCHK(ctx, hipGetLastError());
-    }
-    HIPCHK(ctx, hipStreamSynchronize(st));
-    for (int j = 0; j < J; ++j) S.true_res[j] = std::sqrt(true2[j] / hs.rr0);
   }
   ctx->fwd_valid = o.keep_solutions != 0;
   ctx->fwd_J = J;
@@ -816,10 +919,11 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
     for (DevBuf* b : {&H, &Mu, &Rr, &Pb, &Q, &z, &gd, &gam, &cst}) release(*b);
   };
   const long long ncell = (long long)ctx->nx * ctx->ny * ctx->nz;
-  if ((rc = ensure(ctx, H, vb)) || (rc = ensure(ctx, Mu, vb)) || (rc = ensure(ctx, Rr, vb)) ||
+  const int nH = n_rx <= kAdjointMultishiftMaxRx ? std::min(n_rx, kMaxConcurrentSolves) : 1;
+  if ((rc = ensure(ctx, H, nH * vb)) || (rc = ensure(ctx, Mu, vb)) || (rc = ensure(ctx, Rr, vb)) ||
       (rc = ensure(ctx, Pb, 2 * vb)) || (rc = ensure(ctx, Q, vb)) || (rc = ensure(ctx, z, ctx->n3 * sizeof(double))) ||
       (rc = ensure(ctx, gd, ncell * sizeof(double))) || (rc = ensure(ctx, gam, 2 * (size_t)J * n_rx * sizeof(double))) ||
-      (rc = ensure(ctx, cst, (size_t)(2 * TEM_MAX_SHIFTS * sizeof(double))))) {
+      (rc = ensure(ctx, cst, (size_t)(2 * TEM_MAX_SHIFTS * kMaxConcurrentSolves * sizeof(double))))) {
     cleanup();
     return rc;
   }
@@ -849,42 +953,62 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
     if (e != hipSuccess) break;
     if (n_rx <= kAdjointMultishiftMaxRx) {
       // lambda_j = sum_r gamma_jr (K + s_j M)^-1 q_r: one multi-shift solve per
-      // receiver row (all shifts share its Krylov recurrence), combined on the device
+      // receiver row (all shifts share its Krylov recurrence), up to
+      // kMaxConcurrentSolves rows at once, combined on the device
       e = hipMemsetAsync(Mu.p, 0, vb, st);
-      std::vector<double> qrow(ctx->n3);
       std::vector<double> sre(J), sim(J);
       for (int j = 0; j < J; ++j) {
         sre[j] = -ctx->fwd_xi[2 * j];
         sim[j] = -ctx->fwd_xi[2 * j + 1];
       }
-      std::vector<double> gcol(2 * (size_t)J);
-      for (int r = 0; r < n_rx && e == hipSuccess; ++r) {
-        receiver_row(ctx, ctx->fwd_rx[r], qrow);
-        e = hipMemcpyAsync(ctx->f.p, qrow.data(), ctx->n3 * sizeof(double), hipMemcpyHostToDevice, st);
+      const int nconc = std::min(n_rx, kMaxConcurrentSolves);
+      if ((rc = ensure_slots(ctx, nconc))) {
+        cleanup();
+        return rc;
+      }
+      for (int i = 0; i < nconc; ++i)
+        if ((rc = ensure(ctx, ctx->slots[i].gvec, ctx->n3 * sizeof(double)))) {
+          cleanup();
+          return rc;
+        }
+      std::vector<std::vector<double>> qrows(nconc, std::vector<double>(ctx->n3));
+      std::vector<SolveState> states(nconc);
+      std::vector<double> gcol(2 * (size_t)J * nconc);
+      for (int r_first = 0; r_first < n_rx && e == hipSuccess; r_first += nconc) {
+        const int nb = std::min(nconc, n_rx - r_first);
+        for (int i = 0; i < nb && e == hipSuccess; ++i) {
+          receiver_row(ctx, ctx->fwd_rx[r_first + i], qrows[i]);
+          e = hipMemcpyAsync(ctx->f.p, qrows[i].data(), ctx->n3 * sizeof(double), hipMemcpyHostToDevice, st);
+          if (e == hipSuccess)
+            tem::launch_scale(ctx->n3, ctx->d_dinv, (const double*)ctx->f.p, (double*)ctx->slots[i].gvec.p, st);
+        }
         if (e != hipSuccess) break;
-        tem::launch_scale(ctx->n3, ctx->d_dinv, (const double*)ctx->f.p, (double*)ctx->gvec.p, st);
-        SolveState shs;
+        std::vector<double2*> ys(nb);
+        for (int i = 0; i < nb; ++i) ys[i] = (double2*)H.p + (size_t)i * J * ctx->n3;
         double secs = 0.0;
-        int r2 = multishift_solve(ctx, sre, sim, ctx->fwd_s0, o, (double2*)H.p, (double2*)ctx->P.p, shs, secs);
+        int r2 = multishift_solve(ctx, sre, sim, ctx->fwd_s0, o, nb, ys.data(), states.data(), secs);
         if (r2 == TEM_ENOCONV) S.converged = 0;
         else if (r2 != TEM_OK) {
           cleanup();
           return r2;
         }
-        S.iterations += shs.k;
-        for (int j = 0; j < J; ++j) {
-          S.iters_per_shift[j] += shs.iters[j];
-          S.est_res[j] = std::max(S.est_res[j], shs.est[j] / std::sqrt(shs.rr0));
-          S.unknown_updates += (double)ctx->nunk * shs.iters[j];
-          gcol[2 * j] = gamma[2 * ((size_t)j * n_rx + r)];
-          gcol[2 * j + 1] = gamma[2 * ((size_t)j * n_rx + r) + 1];
+        for (int i = 0; i < nb; ++i) {
+          const SolveState& shs = states[i];
+          S.iterations += shs.k;
+          for (int j = 0; j < J; ++j) {
+            S.iters_per_shift[j] += shs.iters[j];
+            S.est_res[j] = std::max(S.est_res[j], shs.est[j] / std::sqrt(shs.rr0));
+            S.unknown_updates += (double)ctx->nunk * shs.iters[j];
+            gcol[2 * ((size_t)i * J + j)] = gamma[2 * ((size_t)j * n_rx + r_first + i)];
+            gcol[2 * ((size_t)i * J + j) + 1] = gamma[2 * ((size_t)j * n_rx + r_first + i) + 1];
+          }
         }
-        e = hipMemcpyAsync(cst.p, gcol.data(), gcol.size() * sizeof(double), hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) {
-          tem::launch_caxpy_shifts(ctx->g, J, (const double*)cst.p, (const double2*)H.p, (double2*)Mu.p, st);
+        e = hipMemcpyAsync(cst.p, gcol.data(), 2 * (size_t)J * nb * sizeof(double), hipMemcpyHostToDevice, st);
+        for (int i = 0; i < nb && e == hipSuccess; ++i) {
+          tem::launch_caxpy_shifts(ctx->g, J, (const double*)cst.p + 2 * (size_t)i * J, ys[i], (double2*)Mu.p, st);
           e = hipGetLastError();
         }
-        if (e == hipSuccess) e = hipStreamSynchronize(st);  // gcol is reused by the next receiver
+        if (e == hipSuccess) e = hipStreamSynchronize(st);  // gcol and the rows are reused by the next group
       }
       if (e != hipSuccess) break;
       tem::launch_grad_edges(ctx->g, J, (const double2*)Mu.p, (const double2*)ctx->Y[s].p, ctx->d_dinv, shd,
@@ -939,17 +1063,18 @@ void tem_destroy(tem_ctx* ctx) {
   if (!ctx) return;
   hipSetDevice(ctx->device);
   if (ctx->work) hipStreamSynchronize(ctx->work);
-  for (double* p : {ctx->d_axis, ctx->d_sigma, ctx->d_mass, ctx->d_dinv, ctx->d_sqrtm, ctx->d_partials})
+  for (SolveSlot& sl : ctx->slots)
+    if (sl.stream) hipStreamSynchronize(sl.stream);
+  for (double* p : {ctx->d_axis, ctx->d_sigma, ctx->d_mass, ctx->d_dinv, ctx->d_sqrtm})
     if (p) hipFree(p);
-  if (ctx->d_state) hipFree(ctx->d_state);
   if (ctx->d_counters) hipFree(ctx->d_counters);
-  for (DevBuf* b : {&ctx->R, &ctx->pbuf, &ctx->q, &ctx->gvec, &ctx->gc, &ctx->f, &ctx->P, &ctx->C, &ctx->rx,
-                    &ctx->data, &ctx->res, &ctx->cpart, &ctx->sh, &ctx->y32, &ctx->refine, &ctx->cst,
-                    &ctx->cocg_part, &ctx->refine64, &ctx->refdot})
+  for (DevBuf* b : {&ctx->gc, &ctx->f, &ctx->P, &ctx->C, &ctx->rx, &ctx->data, &ctx->res, &ctx->cpart, &ctx->sh,
+                    &ctx->refine, &ctx->cst, &ctx->cocg_part, &ctx->refine64, &ctx->refdot})
     release(*b);
   for (DevBuf& b : ctx->Y) release(b);
-  if (ctx->head_pinned) hipHostFree(ctx->head_pinned);
+  for (SolveSlot& sl : ctx->slots) release_slot(sl);
   if (ctx->order_ev) hipEventDestroy(ctx->order_ev);
+  if (ctx->work_ev) hipEventDestroy(ctx->work_ev);
   if (ctx->work) hipStreamDestroy(ctx->work);
   delete ctx;
 }

@@ -3,10 +3,12 @@
 Requests (a grid, a conductivity model, 1-4 loops, receivers; forward or
 adjoint) arrive over time.  A scheduler admits a request when its device
 footprint fits in the HBM budget and a slot is free; every admitted request
-runs on its own library context and HIP stream in a worker thread (the C
-calls release the GIL), so the graph-replayed solver blocks of different
-requests are in flight on the device at the same time and a request that
-arrives while others run is admitted as soon as memory and a slot free up.
+runs on its own library context in a worker thread (the C calls release the
+GIL).  Within a request the library already solves up to four loop sources
+(or adjoint receiver rows) at once on separate streams, so the graph-replayed
+solver blocks of all admitted requests are in flight on the device together,
+and a request that arrives while others run is admitted as soon as memory
+and a slot free up.
 All requests share one pole/residue set (the channels are the same).
 
 Each request's arithmetic is independent of the others (its own buffers,
@@ -25,17 +27,28 @@ import numpy as np
 from . import tem
 
 
-def footprint_bytes(nx, ny, nz, J, n_src, kind, block=64):
-    """Device bytes a request needs: operator arrays, the Krylov workspace of
-    one multi-shift solve (residual ring, seed vectors, per-shift x_j and p_j)
-    and, for the adjoint, the stored solutions of every source plus the J
-    complex COCG vectors."""
+def footprint_bytes(nx, ny, nz, J, n_src, kind, block=64, n_rx=1, concurrent=4):
+    """Device bytes a request needs (the library's allocations for it):
+    operator arrays; one solver workspace per concurrent multi-shift solve
+    (residual ring of `block` vectors, seed p and q, right-hand side, per-shift
+    p_j); the solutions y_j of every concurrent source (of every source for the
+    adjoint, which keeps them); the residual and contraction scratch; for the
+    adjoint, its right-hand sides per concurrent receiver row and its COCG
+    vectors."""
     n3 = 3 * (nx + 1) * (ny + 1) * (nz + 1)
+    vec = 16 * n3 * J                      # J complex node-padded vectors
     ops = 8 * n3 * 3 + 8 * nx * ny * nz
-    solve = 8 * n3 * (block + 4) + 16 * n3 * J * 2 + 16 * n3
-    keep = 16 * n3 * J * n_src if kind == "adjoint" else 0
-    adj = 16 * n3 * J * 6 + 8 * n3 if kind == "adjoint" else 0
-    return ops + solve + keep + adj
+    conc = min(n_src, concurrent)
+    slots = conc
+    if kind == "adjoint":
+        slots = max(slots, min(n_rx, concurrent))
+    slot = 8 * n3 * (block + 4) + vec + (1 << 20)
+    keep = vec * (n_src if kind == "adjoint" else conc)
+    scratch = vec + 24 * n3
+    adj = 0
+    if kind == "adjoint":
+        adj = vec * (min(n_rx, concurrent) + 5) + 8 * n3
+    return ops + slots * slot + keep + scratch + adj
 
 
 @dataclass
@@ -111,7 +124,8 @@ class Server:
         J = len(self.xi)
         for r in requests:
             wl = r.workload
-            r.footprint = footprint_bytes(len(wl.hx), len(wl.hy), len(wl.hz), J, len(wl.loops), r.kind)
+            r.footprint = footprint_bytes(len(wl.hx), len(wl.hy), len(wl.hz), J, len(wl.loops), r.kind,
+                                          n_rx=len(wl.receivers))
             if r.footprint > self.budget:
                 r.error = "TEM_ENOMEM: request footprint %d exceeds the budget %d" % (r.footprint, self.budget)
         t0 = time.perf_counter()

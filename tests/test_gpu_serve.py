@@ -60,7 +60,8 @@ def test_admission_by_footprint(tem):
     reqs, t = _requests(3)
     fit = rkfit.rkfit(t, 18)
     s, C = rkfit.shifts_and_coefficients(fit)
-    fps = [footprint_bytes(len(r.workload.hx), len(r.workload.hy), len(r.workload.hz), len(s), 1, r.kind) for r in reqs]
+    fps = [footprint_bytes(len(r.workload.hx), len(r.workload.hy), len(r.workload.hz), len(s), len(r.workload.loops),
+                           r.kind, n_rx=len(r.workload.receivers)) for r in reqs]
     srv = Server(-s, C, max_active=8, hbm_budget=max(fps))
     out = srv.run(reqs, realtime=False)
     spans = sorted((r.admitted, r.finished) for r in out)
