@@ -164,11 +164,15 @@ int tem_forward(tem_ctx *ctx, const tem_loop *src, int n_src,
                 double *data, double *fields, tem_stats *stats);
 
 /* Adjoint (Sec. 4): given w[(s*T + k)*n_rx + r] = dphi/d data (host) for the
- * last tem_forward call (which must have set keep_solutions), compute
+ * last tem_forward call, compute
  *   grad[c] = dphi/d ln sigma_c = -Re sum_s sum_j s_j lambda_j^T (dM/d ln sigma_c) x_j,
  *   (K + s_j M) lambda_j = sum_k c_j(t_k) Q^T w_k,  s_j = -xi_j,
- * for every cell c (grad[nz*ny*nx], host).  Returns TEM_ESTATE if there is
- * no matching forward state. */
+ * for every cell c (grad[nz*ny*nx], host).  The forward solutions x_j are
+ * the ones kept by a forward with keep_solutions; without it they are
+ * recomputed here source by source (one more FP64 multi-shift solve per
+ * source, holding one source's solutions instead of all), with the same
+ * result for a precision-0 forward.  Returns TEM_ESTATE if no forward ran
+ * since the last tem_set_conductivity. */
 int tem_adjoint(tem_ctx *ctx, const double *w, double *grad_log_sigma, tem_stats *stats);
 
 /* Copy the stored solutions x_j of source s (storage edge order, complex):

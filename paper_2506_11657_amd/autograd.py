@@ -17,8 +17,12 @@ import torch
 class ReceiverData(torch.autograd.Function):
     @staticmethod
     def forward(fctx, log_sigma, ctx, loops, receivers, xi, c, opts):
+        opts = dict(opts)
+        # recompute=True keeps no forward solutions on the device: the backward
+        # solves for them again (one more multi-shift solve per source)
+        keep = not opts.pop("recompute", False)
         ctx.set_conductivity(log_sigma.detach(), log=True)
-        data, _ = ctx.forward(loops, receivers, xi, c, keep_solutions=True, **opts)
+        data, _ = ctx.forward(loops, receivers, xi, c, keep_solutions=keep, **opts)
         fctx.tem_ctx = ctx
         fctx.generation = ctx.generation
         fctx.sigma_shape = log_sigma.shape
@@ -41,5 +45,7 @@ class ReceiverData(torch.autograd.Function):
 
 def receiver_data(log_sigma, ctx, loops, receivers, xi, c, **opts):
     """dB_z/dt data (n_src, T, n_rx) of the model ln sigma (nz, ny, nx), with a
-    gradient w.r.t. ln sigma through the adjoint solves."""
+    gradient w.r.t. ln sigma through the adjoint solves.  opts go to
+    Context.forward; recompute=True trades memory for one more solve per
+    source in the backward."""
     return ReceiverData.apply(log_sigma, ctx, loops, receivers, xi, c, opts)

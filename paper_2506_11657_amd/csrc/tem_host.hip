@@ -76,7 +76,8 @@ struct tem_ctx {
   DevBuf refine64, refdot;             // precision 1: FP64 corrections d_j and (A + s_j) d_j; step lengths
   std::vector<DevBuf> Y;  // per source (kept) or one
   // stored forward state for the adjoint
-  bool fwd_valid = false;
+  bool fwd_meta = false;   // the last forward's sources, receivers, poles and options are recorded
+  bool fwd_valid = false;  // ... and its solutions are kept on the device
   int fwd_J = 0, fwd_T = 0, fwd_nsrc = 0, fwd_nrx = 0;
   double fwd_s0 = 0.0;
   std::vector<double> fwd_xi, fwd_c;
@@ -583,6 +584,7 @@ int tem_set_conductivity(tem_ctx* ctx, const double* sigma, int flags) {
   HIPCHK(ctx, hipStreamSynchronize(ctx->work));
   ctx->has_sigma = true;
   ctx->fwd_valid = false;
+  ctx->fwd_meta = false;
   return TEM_OK;
 }
 
@@ -591,6 +593,7 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
                 tem_stats* stats) {
   auto t_start = std::chrono::steady_clock::now();
   if (!ctx) return fail(nullptr, TEM_EINVAL, "ctx is NULL");
+  ctx->fwd_valid = ctx->fwd_meta = false;  // a new forward replaces the stored one, also when it fails
   if (!ctx->has_sigma) return fail(ctx, TEM_ESTATE, "conductivity not set");
   int rc;
   if ((rc = check_loops(ctx, src, n_src))) return rc;
@@ -830,6 +833,7 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
     }
   }
   ctx->fwd_valid = o.keep_solutions != 0;
+  ctx->fwd_meta = true;
   ctx->fwd_J = J;
   ctx->fwd_T = T;
   ctx->fwd_nsrc = n_src;
@@ -902,7 +906,7 @@ int tem_apply(tem_ctx* ctx, double shift_re, double shift_im, const double* x, d
 int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
   auto t_start = std::chrono::steady_clock::now();
   if (!ctx) return fail(nullptr, TEM_EINVAL, "ctx is NULL");
-  if (!ctx->fwd_valid) return fail(ctx, TEM_ESTATE, "tem_adjoint needs a preceding tem_forward with keep_solutions");
+  if (!ctx->fwd_meta) return fail(ctx, TEM_ESTATE, "tem_adjoint needs a preceding tem_forward");
   if (!w || !grad) return fail(ctx, TEM_EINVAL, "w and grad must not be NULL");
   const int J = ctx->fwd_J, T = ctx->fwd_T, n_rx = ctx->fwd_nrx, n_src = ctx->fwd_nsrc;
   if (n_rx < 1) return fail(ctx, TEM_EINVAL, "the forward had no receivers");
@@ -951,6 +955,36 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
       }
     e = hipMemcpyAsync(gam.p, gamma.data(), gamma.size() * sizeof(double), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) break;
+    // forward solutions x_j of source s: stored, or recomputed now (one more
+    // FP64 multi-shift solve; only one source's solutions are held at a time)
+    double2* Ys = (double2*)ctx->Y[ctx->fwd_valid ? s : 0].p;
+    if (!ctx->fwd_valid) {
+      std::vector<double> fsrc(ctx->n3), sre(J), sim(J);
+      for (int j = 0; j < J; ++j) {
+        sre[j] = -ctx->fwd_xi[2 * j];
+        sim[j] = -ctx->fwd_xi[2 * j + 1];
+      }
+      if ((rc = ensure_slots(ctx, 1)) || (rc = ensure(ctx, ctx->slots[0].gvec, ctx->n3 * sizeof(double)))) {
+        cleanup();
+        return rc;
+      }
+      loop_source(ctx, ctx->fwd_src[s], fsrc);
+      e = hipMemcpyAsync(ctx->f.p, fsrc.data(), ctx->n3 * sizeof(double), hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) break;
+      tem::launch_scale(ctx->n3, ctx->d_dinv, (const double*)ctx->f.p, (double*)ctx->slots[0].gvec.p, st);
+      tem_solve_opts of = o;  // an FP64 solve, to the FP64 default when the forward was precision 1
+      if (of.precision == 1) of.rtol = 1e-12;
+      of.precision = 0;
+      SolveState fst;
+      double secs = 0.0;
+      const int r1 = multishift_solve(ctx, sre, sim, ctx->fwd_s0, of, 1, &Ys, &fst, secs);
+      if (r1 == TEM_ENOCONV) S.converged = 0;
+      else if (r1 != TEM_OK) {
+        cleanup();
+        return r1;
+      }
+      for (int j = 0; j < J; ++j) S.unknown_updates += (double)ctx->nunk * fst.iters[j];
+    }
     if (n_rx <= kAdjointMultishiftMaxRx) {
       // lambda_j = sum_r gamma_jr (K + s_j M)^-1 q_r: one multi-shift solve per
       // receiver row (all shifts share its Krylov recurrence), up to
@@ -1011,8 +1045,8 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
         if (e == hipSuccess) e = hipStreamSynchronize(st);  // gcol and the rows are reused by the next group
       }
       if (e != hipSuccess) break;
-      tem::launch_grad_edges(ctx->g, J, (const double2*)Mu.p, (const double2*)ctx->Y[s].p, ctx->d_dinv, shd,
-                             shd + TEM_MAX_SHIFTS, (double*)z.p, st);
+      tem::launch_grad_edges(ctx->g, J, (const double2*)Mu.p, Ys, ctx->d_dinv, shd, shd + TEM_MAX_SHIFTS,
+                             (double*)z.p, st);
       continue;
     }
     if (e == hipSuccess) e = hipMemsetAsync(H.p, 0, vb, st);
@@ -1036,8 +1070,8 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
       S.est_res[j] = hs->hn2[j] > 0 ? std::sqrt(hs->rn2[j] / hs->hn2[j]) : 0.0;
       S.unknown_updates += (double)ctx->nunk * hs->iters[j];
     }
-    tem::launch_grad_edges(ctx->g, J, (const double2*)Mu.p, (const double2*)ctx->Y[s].p, ctx->d_dinv, shd,
-                           shd + TEM_MAX_SHIFTS, (double*)z.p, st);
+    tem::launch_grad_edges(ctx->g, J, (const double2*)Mu.p, Ys, ctx->d_dinv, shd, shd + TEM_MAX_SHIFTS,
+                           (double*)z.p, st);
   }
   if (e == hipSuccess) {
     tem::launch_grad_cells(ctx->g, ctx->d_sigma, (const double*)z.p, (double*)gd.p, st);

@@ -121,3 +121,21 @@ def test_autograd_function_matches_adjoint(tem):
     ctx.forward(wl.loops, wl.receivers, -s, C)
     with pytest.raises(RuntimeError):
         d2.sum().backward()
+
+
+def test_adjoint_recomputes_solutions_when_not_kept(tem):
+    """A forward without keep_solutions stores no solutions; the adjoint then
+    solves for them again source by source and gives the same gradient, bit
+    for bit, as the adjoint of a forward that kept them."""
+    wl, s, C = _misfit_case(6, 16)
+    wl.loops = [W.Loop(1, 4, 1, 4, 1.0), W.Loop(3, 6, 2, 5, -0.5)]
+    ctx = tem.Context.from_workload(wl)
+    rng = np.random.default_rng(4)
+    w = rng.standard_normal((2, 6, len(wl.receivers)))
+    ctx.forward(wl.loops, wl.receivers, -s, C, keep_solutions=True)
+    g_keep, _ = ctx.adjoint(w)
+    ctx.forward(wl.loops, wl.receivers, -s, C, keep_solutions=False)
+    with pytest.raises(tem.TemError):
+        ctx.solutions(0)
+    g_re, st = ctx.adjoint(w)
+    assert np.array_equal(g_keep, g_re)

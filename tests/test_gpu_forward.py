@@ -189,3 +189,48 @@ def test_noconv_and_errors(tem):
     bad[0, 0, 0] = -1.0
     with pytest.raises(tem.TemError):
         ctx.set_conductivity(bad)
+
+
+def test_max_shifts_and_channels_no_receivers(tem):
+    """J = 64 shifts (the maximum; the coefficient table forces 16-iteration
+    blocks) and T = 64 channels with no receivers (fields only): every shift
+    matches the banded direct solve and the fields equal Re(X C)."""
+    import torch
+    wl = W.small_case(6, seed=8, t=W.log_channels(1e-5, 1e-3, 64))
+    P = yee.Problem(wl)
+    rng = np.random.default_rng(12)
+    # 64 shifts with Re s > 0 spread over the spectrum of the scaled operator
+    s = 10 ** rng.uniform(2, 7, 64) * np.exp(1j * rng.uniform(-1.2, 1.2, 64))
+    C = rng.standard_normal((64, 64)) + 1j * rng.standard_normal((64, 64))
+    ctx = tem.Context.from_workload(wl)
+    fields = torch.zeros((1, 64, ctx.n_storage), dtype=torch.float64, device="cuda")
+    data, st = ctx.forward(wl.loops, [], -s, C, fields=fields, keep_solutions=True)
+    assert st["converged"] and data.shape == (1, 64, 0)
+    X = ctx.solutions(0)[:, P.idx].T
+    Xo = direct.solve_shifted(P, s, P.F[:, 0], "banded")
+    ex = direct.m_norm(P, X - Xo) / direct.m_norm(P, Xo)
+    assert ex.max() <= 1e-8
+    U = fields[0].cpu().numpy()
+    Xs = ctx.solutions(0)
+    ref = (C.T @ Xs).real
+    assert np.all(np.abs(U - ref) <= 1e-13 * (np.abs(C).T @ np.abs(Xs)) + 1e-300)
+
+
+def test_odd_degree_real_pole_and_single_shift(tem):
+    """An odd degree gives a real pole (c_j without the factor 2); the forward
+    with that family matches the oracle, and so does a single real shift."""
+    wl = W.small_case(7, seed=6, t=W.log_channels(1e-5, 1e-3, 9))
+    fit = rkfit.rkfit(wl.t, 15)
+    s, C = rkfit.shifts_and_coefficients(fit)
+    assert np.any(np.abs(s.imag) == 0.0)
+    P = yee.Problem(wl)
+    ctx = tem.Context.from_workload(wl)
+    for ss, CC in ((s, C), (s[np.abs(s.imag) == 0.0][:1], C[np.abs(s.imag) == 0.0][:1])):
+        data, st = ctx.forward(wl.loops, wl.receivers, -ss, CC, keep_solutions=True)
+        X = ctx.solutions(0)[:, P.idx].T
+        Xo = direct.solve_shifted(P, ss, P.F[:, 0], "banded")
+        assert (direct.m_norm(P, X - Xo) / direct.m_norm(P, Xo)).max() <= 1e-8
+        d_or = (P.Q @ direct.contract(Xo, CC)).T
+        Sd = np.abs(CC).T @ direct.m_norm(P, Xo)
+        qn = np.sqrt(np.asarray(P.Q.multiply(P.Q) @ (1.0 / P.M)).ravel())
+        assert np.all(np.abs(data[0] - d_or) <= 1e-8 * np.abs(d_or) + 1e-10 * np.outer(Sd, qn))
