@@ -43,7 +43,7 @@ def algorithmic_bytes(kind, ctx_dims, J_apply, B):
 
 # HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE runs, keyed by the
 # kernel source it was measured on (bytes per launch; see profiles/); None once the source changes
-TRAFFIC = {("c33100de0394", "graded64", "seed_stencil"): (12231.0 + 12544.1) * 1024.0}
+TRAFFIC = {("3eca1242424b", "graded64", "seed_stencil"): (12231.3 + 12544.1) * 1024.0}
 
 
 def kernel_source_hash():
@@ -116,6 +116,66 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def adjoint_bench(args):
+    """Differentiation workload at 64^3: blocky true and current models on the
+    graded grid, 30 surface receivers, 40 channels, misfit 1/2 ||d - d_obs||^2.
+    Times one forward (solutions kept) plus the adjoint gradient w.r.t. ln sigma,
+    then checks the gradient against central differences (step 1e-3 in ln sigma)
+    of the GPU forward on seeded cells of the sensitive region, as many as the
+    time budget allows."""
+    import tem_workloads as W
+    from paper_2506_11657_amd import tem
+    true_wl, cur_wl = W.cfg_inverse(64)
+    xi, c, err = tem.poles(cur_wl.t, cur_wl.degree)
+    t_start = time.perf_counter()
+    ctx = tem.Context.from_workload(true_wl)
+    d_obs, _ = ctx.forward(true_wl.loops, true_wl.receivers, xi, c)
+    print("observed data (true model) in %.1f s" % (time.perf_counter() - t_start), file=sys.stderr, flush=True)
+    ctx.set_conductivity(cur_wl.sigma)
+    t0 = time.perf_counter()
+    d, st = ctx.forward(cur_wl.loops, cur_wl.receivers, xi, c, keep_solutions=True)
+    t1 = time.perf_counter()
+    g, sa = ctx.adjoint(d - d_obs)
+    t2 = time.perf_counter()
+    print("forward %.1f s (%d iterations), adjoint %.1f s (%d seed iterations over %d receiver solves)"
+          % (t1 - t0, st["iterations"], t2 - t1, sa["iterations"], len(cur_wl.receivers)), file=sys.stderr,
+          flush=True)
+    phi0 = 0.5 * float(np.sum((d - d_obs) ** 2))
+    rng = np.random.default_rng(6)
+    cand = np.argwhere(np.abs(g) >= 1e-2 * np.abs(g).max())
+    order = rng.permutation(len(cand))
+    h, checks = 1e-3, []
+    for idx in order[:args.fd_cells]:
+        if time.perf_counter() - t_start > args.time_budget:
+            break
+        k, j, i = (int(v) for v in cand[idx])
+        vals = []
+        for sg in (+1, -1):
+            sig = cur_wl.sigma.copy()
+            sig[k, j, i] *= np.exp(sg * h)
+            ctx.set_conductivity(sig)
+            dd, _ = ctx.forward(cur_wl.loops, cur_wl.receivers, xi, c)
+            vals.append(0.5 * float(np.sum((dd - d_obs) ** 2)))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        ok = abs(fd - g[k, j, i]) <= 1e-4 * abs(g[k, j, i]) + 1e-6 * np.abs(g).max()
+        checks.append({"cell": [k, j, i], "adjoint": float(g[k, j, i]), "fd": fd,
+                       "rel_diff": abs(fd - g[k, j, i]) / abs(g[k, j, i]), "pass": bool(ok)})
+        print("cell %s: adjoint %.6e, central difference %.6e, rel diff %.2e" % ((k, j, i), g[k, j, i], fd,
+              checks[-1]["rel_diff"]), file=sys.stderr, flush=True)
+    n_unknowns = ctx.n_unknowns
+    ctx.close()
+    out = {"metric": METRIC, "value": 1.0 / (t2 - t0), "unit": "gradients/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": 1e3 * (t2 - t0), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic (seeded)",
+           "config": {"workload": "differentiation, 64^3 graded, blocky log-conductivity, 30 receivers, 40 channels",
+                      "n_unknowns": n_unknowns},
+           "forward_s": t1 - t0, "adjoint_s": t2 - t1, "misfit": phi0,
+           "unknown_updates_per_s": (st["unknown_updates"] + sa["unknown_updates"]) / (t2 - t0),
+           "fd_check": {"step_ln_sigma": h, "bar": "|fd - adj| <= 1e-4 |adj| + 1e-6 max|g|", "cells": checks,
+                        "all_pass": all(x["pass"] for x in checks)}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +194,11 @@ def main():
     ap.add_argument("--serve", type=int, default=0,
                     help="instead of the forward benchmark, serve the first N requests of the seeded "
                          "200 req/s trace (grids 32..96, forward and adjoint, 1-4 loops)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="instead of the forward benchmark, the 64^3 differentiation workload: forward + adjoint "
+                         "timing and a central-difference check of the gradient")
+    ap.add_argument("--fd-cells", type=int, default=6)
+    ap.add_argument("--time-budget", type=float, default=900.0, help="--adjoint: stop starting FD cells after this")
     ap.add_argument("--serve-max-active", type=int, default=4)
     ap.add_argument("--serve-compare", action="store_true",
                     help="also serve the same trace one request at a time (no overlap)")
@@ -148,6 +213,8 @@ def main():
     from paper_2506_11657_amd import tem
     if args.serve:
         return serve_bench(args)
+    if args.adjoint:
+        return adjoint_bench(args)
 
     wl = {"graded64": W.cfg_graded64, "plain16": W.cfg_plain16, "blocky128": W.cfg_blocky128}[args.config]()
     xi, c, err = tem.poles(wl.t, wl.degree)

@@ -20,7 +20,10 @@ static_assert(sizeof(tem::SolveHead) <= 4096, "pinned head buffer");
 namespace {
 
 thread_local std::string g_global_error;
-constexpr int kAdjointMultishiftMaxRx = 12;  // adjoint by per-receiver multi-shift solves up to this many receivers
+// Adjoint by one multi-shift solve per receiver row up to this many receivers
+// (about n_rx seed sweeps); beyond it one batched COCG over the J shifted
+// systems (about J complex solves) costs less.
+constexpr int kAdjointMultishiftMaxRx = 64;
 // precision 1: the sweep with complex FP32 shift vectors stops at this scaled
 // residual (their storage rounding sits near it); FP64 residual refinement then
 // drives every shift to the requested rtol (default kRefineTarget), each pass

@@ -125,7 +125,6 @@ void launch_scatter_storage(const GridArgs& g, const double2* xpub, const double
 void launch_gather_storage(const GridArgs& g, const double2* xpad, const double* w, double2* xpub, hipStream_t s);
 long long storage_edges(const GridArgs& g);
 int cstencil_partials(const GridArgs& g);
-int reduce_blocks(long long n);
 int seed_stencil_blocks(const GridArgs& g);
 // adjoint: batched COCG (state is an opaque device struct of cocg_state_bytes())
 size_t cocg_state_bytes();

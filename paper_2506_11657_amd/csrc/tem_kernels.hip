@@ -88,14 +88,6 @@ __device__ bool publish_partial(double v, double* partials, unsigned int* counte
   return last;
 }
 
-// Fixed-order sum of n partials by one block.
-__device__ double sum_partials(const double* partials, int n, double* lds) {
-  double s = 0.0;
-  for (int i = flat_tid(); i < n; i += flat_threads())
-    s += __hip_atomic_load(partials + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return block_sum(s, lds);
-}
-
 __device__ __forceinline__ long long node_of(const GridArgs& g, int i, int j, int k) {
   return ((long long)k * g.py + j) * g.px + i;
 }
@@ -277,12 +269,7 @@ __device__ void stencil_tile(const GridArgs& g, const double* __restrict__ dinv,
 // combine(raw) forms the value, which is scaled by M^-1/2 into LDS.  The face
 // fluxes of KZ + 1 planes are formed in LDS from the 1-D width products, and
 // emit(v, c, (K p')_c, u, M^-1/2) receives every owned edge.
-// PF: fetch into registers before pre() (true) or after it, straight into
-// LDS (false, fewer registers).  NOPHI: each thread forms the nine face fluxes
-// its three edges need directly from the staged field instead of staging all
-// fluxes of the tile in LDS first (no flux array, one barrier fewer).
-template <int TX, int TY, int KZ, bool PF = true, bool NOPHI = false, typename FetchFn, typename PreFn,
-          typename CombineFn, typename EmitFn>
+template <int TX, int TY, int KZ, typename FetchFn, typename PreFn, typename CombineFn, typename EmitFn>
 __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ dinv, int zb, FetchFn fetch, PreFn pre,
                                 CombineFn combine, EmitFn emit) {
   constexpr int NP = KZ + 2;                                // planes loaded
@@ -292,6 +279,7 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
   constexpr int NL = (NP * NE + NT - 1) / NT;               // staged entries per thread
   using Raw = decltype(fetch(0LL, 0));
   __shared__ double sp[NP][3][TY + 2][TX + 2];
+  __shared__ double phi[KZ + 1][3][TY + 1][TX + 1];
   // 1-D weights of the block's flux nodes: x (li = 0..TX), y (lj = 0..TY), z (pl = 0..KZ)
   __shared__ double wxh[TX + 1], wxi[TX + 1], wxd[TX + 1];
   __shared__ double wyh[TY + 1], wyi[TY + 1], wyd[TY + 1];
@@ -302,50 +290,34 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
   const int k0 = zb * KZ;
   const int i = i0 + tx, j = j0 + ty;
   const bool own = (i < g.nx) && (j < g.ny);
-  // 1. weights; with PF also every load (own raw values, staged raw values, M^-1/2)
+  // 1. issue every load: own raw values, staged raw values and M^-1/2, weights
   Raw ou[KZ][3];
   double od[KZ][3];
-  auto load_own = [&]() {
 #pragma unroll
-    for (int z = 0; z < KZ; ++z) {
-      const int kk = k0 + z;
-      const bool ok = own && kk < g.nz;
-      const long long v = ok ? node_of(g, i, j, kk) : 0;
+  for (int z = 0; z < KZ; ++z) {
+    const int kk = k0 + z;
+    const bool ok = own && kk < g.nz;
+    const long long v = ok ? node_of(g, i, j, kk) : 0;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        od[z][c] = ok ? dinv[c * g.nn + v] : 0.0;
-        ou[z][c] = ok ? fetch(v, c) : Raw{};
-      }
+    for (int c = 0; c < 3; ++c) {
+      od[z][c] = ok ? dinv[c * g.nn + v] : 0.0;
+      ou[z][c] = ok ? fetch(v, c) : Raw{};
     }
-  };
-  auto staged = [&](int l, int& pl, int& li, int& lj, long long& v) {
+  }
+  Raw hr[NL][3];
+  double hd[NL][3];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
     const int e = tid + l * NT;
-    pl = e / NE;
-    const int r = e % NE;
-    li = r % (TX + 2);
-    lj = r / (TX + 2);
+    const int pl = e / NE, r = e % NE;
+    const int li = r % (TX + 2), lj = r / (TX + 2);
     const int gi = i0 - 1 + li, gj = j0 - 1 + lj, kk = k0 - 1 + pl;
     const bool in = e < NP * NE && gi >= 0 && gi < g.px && gj >= 0 && gj < g.py && kk >= 0 && kk < g.pz;
-    v = in ? node_of(g, gi, gj, kk) : -1;
-    return e < NP * NE;
-  };
-  Raw hr[PF ? NL : 1][3];
-  double hd[PF ? NL : 1][3];
-  if constexpr (PF) {
-    load_own();
+    const long long v = in ? node_of(g, gi, gj, kk) : 0;
 #pragma unroll
-    for (int l = 0; l < NL; ++l) {
-      const int e = tid + l * NT;
-      const int pl = e / NE, r = e % NE;
-      const int li = r % (TX + 2), lj = r / (TX + 2);
-      const int gi = i0 - 1 + li, gj = j0 - 1 + lj, kk = k0 - 1 + pl;
-      const bool in = e < NP * NE && gi >= 0 && gi < g.px && gj >= 0 && gj < g.py && kk >= 0 && kk < g.pz;
-      const long long v = in ? node_of(g, gi, gj, kk) : 0;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        hd[l][c] = in ? dinv[c * g.nn + v] : 0.0;
-        hr[l][c] = in ? fetch(v, c) : Raw{};
-      }
+    for (int c = 0; c < 3; ++c) {
+      hd[l][c] = in ? dinv[c * g.nn + v] : 0.0;
+      hr[l][c] = in ? fetch(v, c) : Raw{};
     }
   }
   for (int e = tid; e < (TX + 1) + (TY + 1) + (KZ + 1); e += NT) {
@@ -369,107 +341,57 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
       wzd[q] = ok ? g.dw[2][kk] : 0.0;
     }
   }
-  // 2. the caller's reduction (overlapping the loads above with PF)
+  // 2. the caller's reduction overlaps the loads above
   pre();
   // 3. staged values into LDS
-  if constexpr (PF) {
 #pragma unroll
-    for (int l = 0; l < NL; ++l) {
-      const int e = tid + l * NT;
-      if (e < NP * NE) {
-        const int pl = e / NE, r = e % NE;
-        const int li = r % (TX + 2), lj = r / (TX + 2);
+  for (int l = 0; l < NL; ++l) {
+    const int e = tid + l * NT;
+    if (e < NP * NE) {
+      const int pl = e / NE, r = e % NE;
+      const int li = r % (TX + 2), lj = r / (TX + 2);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) sp[pl][c][lj][li] = hd[l][c] * combine(hr[l][c]);
-      }
-    }
-  } else {
-    load_own();
-    for (int l = 0; l < NL; ++l) {
-      int pl, li, lj;
-      long long v;
-      if (staged(l, pl, li, lj, v))
-#pragma unroll
-        for (int c = 0; c < 3; ++c) sp[pl][c][lj][li] = v >= 0 ? dinv[c * g.nn + v] * combine(fetch(v, c)) : 0.0;
+      for (int c = 0; c < 3; ++c) sp[pl][c][lj][li] = hd[l][c] * combine(hr[l][c]);
     }
   }
   __syncthreads();
-  // face fluxes w_f * (circulation) of the node with tile coordinates (li, lj)
-  // at staged plane pl (node plane kk = k0 - 1 + pl; planes pl and pl + 1)
-  auto flux = [&](int comp, int li, int lj, int pl) -> double {
+  // fluxes of planes k0-1 .. k0+KZ-1 (plane index pl: kk = k0 - 1 + pl)
+  for (int e = tid; e < (KZ + 1) * NF; e += NT) {
+    const int pl = e / NF, r = e % NF;
+    const int li = r % (TX + 1), lj = r / (TX + 1);
     const int gi = i0 - 1 + li, gj = j0 - 1 + lj, kk = k0 - 1 + pl;
-    if (gi < 0 || gj < 0 || kk < 0 || gi > g.nx || gj > g.ny || kk > g.nz) return 0.0;
-    const double hxi = wxh[li], hyj = wyh[lj], hzk = wzh[pl];
-    const int a = pl, b = pl + 1;
-    if (comp == 0)
-      return wxd[li] * wyi[lj] * wzi[pl] *
-             (hyj * sp[a][1][lj][li] + hzk * sp[a][2][lj + 1][li] - hyj * sp[b][1][lj][li] - hzk * sp[a][2][lj][li]);
-    if (comp == 1)
-      return wyd[lj] * wzi[pl] * wxi[li] *
-             (hzk * sp[a][2][lj][li] + hxi * sp[b][0][lj][li] - hzk * sp[a][2][lj][li + 1] - hxi * sp[a][0][lj][li]);
-    return wzd[pl] * wxi[li] * wyi[lj] *
-           (hxi * sp[a][0][lj][li] + hyj * sp[a][1][lj][li + 1] - hxi * sp[a][0][lj + 1][li] - hyj * sp[a][1][lj][li]);
-  };
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if (gi >= 0 && gj >= 0 && kk >= 0 && gi <= g.nx && gj <= g.ny && kk <= g.nz) {
+      const double hxi = wxh[li], hyj = wyh[lj], hzk = wzh[pl];
+      const double wx = wxd[li] * wyi[lj] * wzi[pl];
+      const double wy = wyd[lj] * wzi[pl] * wxi[li];
+      const double wz = wzd[pl] * wxi[li] * wyi[lj];
+      const int a = pl, b = pl + 1;  // planes kk and kk+1 in sp
+      fx = wx * (hyj * sp[a][1][lj][li] + hzk * sp[a][2][lj + 1][li] - hyj * sp[b][1][lj][li] - hzk * sp[a][2][lj][li]);
+      fy = wy * (hzk * sp[a][2][lj][li] + hxi * sp[b][0][lj][li] - hzk * sp[a][2][lj][li + 1] - hxi * sp[a][0][lj][li]);
+      fz = wz * (hxi * sp[a][0][lj][li] + hyj * sp[a][1][lj][li + 1] - hxi * sp[a][0][lj + 1][li] - hyj * sp[a][1][lj][li]);
+    }
+    phi[pl][0][lj][li] = fx;
+    phi[pl][1][lj][li] = fy;
+    phi[pl][2][lj][li] = fz;
+  }
+  __syncthreads();
+  if (!own) return;
   const int li = tx + 1, lj = ty + 1;
-  if constexpr (NOPHI) {
-    if (!own) return;
-    const double ohx = g.h[0][i], ohy = g.h[1][j];
+  const double ohx = g.h[0][i], ohy = g.h[1][j];
 #pragma unroll
-    for (int z = 0; z < KZ; ++z) {
-      const int kk = k0 + z;
-      if (kk >= g.nz) break;
-      const int p = z + 1;  // staged plane of kk
-      const double fx = flux(0, li, lj, p), fy = flux(1, li, lj, p), fz = flux(2, li, lj, p);
-      const double kpx = ohx * (flux(1, li, lj, p - 1) - fy + fz - flux(2, li, lj - 1, p));
-      const double kpy = ohy * (flux(2, li - 1, lj, p) - fz + fx - flux(0, li, lj, p - 1));
-      const double kpz = g.h[2][kk] * (flux(0, li, lj - 1, p) - fx + fy - flux(1, li - 1, lj, p));
-      const long long v = node_of(g, i, j, kk);
-      emit(v, 0, kpx, ou[z][0], od[z][0]);
-      emit(v, 1, kpy, ou[z][1], od[z][1]);
-      emit(v, 2, kpz, ou[z][2], od[z][2]);
-    }
-  } else {
-    __shared__ double phi[KZ + 1][3][TY + 1][TX + 1];
-    // fluxes of planes k0-1 .. k0+KZ-1 (plane index pl: kk = k0 - 1 + pl)
-    for (int e = tid; e < (KZ + 1) * NF; e += NT) {
-      const int pl = e / NF, r = e % NF;
-      const int fi = r % (TX + 1), fj = r / (TX + 1);
-      const int gi = i0 - 1 + fi, gj = j0 - 1 + fj, kk = k0 - 1 + pl;
-      double fx = 0.0, fy = 0.0, fz = 0.0;
-      if (gi >= 0 && gj >= 0 && kk >= 0 && gi <= g.nx && gj <= g.ny && kk <= g.nz) {
-        const double hxi = wxh[fi], hyj = wyh[fj], hzk = wzh[pl];
-        const double wx = wxd[fi] * wyi[fj] * wzi[pl];
-        const double wy = wyd[fj] * wzi[pl] * wxi[fi];
-        const double wz = wzd[pl] * wxi[fi] * wyi[fj];
-        const int a = pl, b = pl + 1;  // planes kk and kk+1 in sp
-        fx = wx * (hyj * sp[a][1][fj][fi] + hzk * sp[a][2][fj + 1][fi] - hyj * sp[b][1][fj][fi] -
-                   hzk * sp[a][2][fj][fi]);
-        fy = wy * (hzk * sp[a][2][fj][fi] + hxi * sp[b][0][fj][fi] - hzk * sp[a][2][fj][fi + 1] -
-                   hxi * sp[a][0][fj][fi]);
-        fz = wz * (hxi * sp[a][0][fj][fi] + hyj * sp[a][1][fj][fi + 1] - hxi * sp[a][0][fj + 1][fi] -
-                   hyj * sp[a][1][fj][fi]);
-      }
-      phi[pl][0][fj][fi] = fx;
-      phi[pl][1][fj][fi] = fy;
-      phi[pl][2][fj][fi] = fz;
-    }
-    __syncthreads();
-    if (!own) return;
-    const double ohx = g.h[0][i], ohy = g.h[1][j];
-#pragma unroll
-    for (int z = 0; z < KZ; ++z) {
-      const int kk = k0 + z;
-      if (kk >= g.nz) break;
-      const int p = z + 1;  // flux plane of kk
-      const double fx = phi[p][0][lj][li], fy = phi[p][1][lj][li], fz = phi[p][2][lj][li];
-      const double kpx = ohx * (phi[p - 1][1][lj][li] - fy + fz - phi[p][2][lj - 1][li]);
-      const double kpy = ohy * (phi[p][2][lj][li - 1] - fz + fx - phi[p - 1][0][lj][li]);
-      const double kpz = g.h[2][kk] * (phi[p][0][lj - 1][li] - fx + fy - phi[p][1][lj][li - 1]);
-      const long long v = node_of(g, i, j, kk);
-      emit(v, 0, kpx, ou[z][0], od[z][0]);
-      emit(v, 1, kpy, ou[z][1], od[z][1]);
-      emit(v, 2, kpz, ou[z][2], od[z][2]);
-    }
+  for (int z = 0; z < KZ; ++z) {
+    const int kk = k0 + z;
+    if (kk >= g.nz) break;
+    const int p = z + 1;  // flux plane of kk
+    const double fx = phi[p][0][lj][li], fy = phi[p][1][lj][li], fz = phi[p][2][lj][li];
+    const double kpx = ohx * (phi[p - 1][1][lj][li] - fy + fz - phi[p][2][lj - 1][li]);
+    const double kpy = ohy * (phi[p][2][lj][li - 1] - fz + fx - phi[p - 1][0][lj][li]);
+    const double kpz = g.h[2][kk] * (phi[p][0][lj - 1][li] - fx + fy - phi[p][1][lj][li - 1]);
+    const long long v = node_of(g, i, j, kk);
+    emit(v, 0, kpx, ou[z][0], od[z][0]);
+    emit(v, 1, kpy, ou[z][1], od[z][1]);
+    emit(v, 2, kpz, ou[z][2], od[z][2]);
   }
 }
 
@@ -499,11 +421,10 @@ __device__ double sum_prev(const double* __restrict__ partials, int n, double* l
 // block and the next kernel sums them in a fixed order, so results are
 // bitwise repeatable and no device-scope fences are needed.
 // ---------------------------------------------------------------------------
-// WPE waves per SIMD: 4 keeps two 512-thread tiles with flux staging resident
-// per CU (their LDS fits two), so the prefetched registers must fit in 128
-// VGPRs; the variants without flux staging and prefetch aim at three tiles.
-template <int TX, int TY, int KZ, bool B3D, bool PF = true, bool NOPHI = false, int WPE = 4>
-__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) k_seed_stencil(GridArgs g, const double* __restrict__ r,
+// 4 waves per SIMD keeps two 512-thread tiles resident per CU (the LDS of
+// two tiles fits); the staged registers must then fit in 128 VGPRs
+template <int TX, int TY, int KZ, bool B3D>
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(4))) k_seed_stencil(GridArgs g, const double* __restrict__ r,
                                                           const double* __restrict__ pold,
                                                           double* __restrict__ pnew, double* __restrict__ q,
                                                           const double* __restrict__ dinv, double s0,
@@ -545,7 +466,7 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE
     auto fetch = [&](long long v, int c) { return RP{r[c * g.nn + v], pold[c * g.nn + v]}; };
     auto combine = [&](const RP& x) { return x.r + beta * x.p; };
     auto emit_raw = [&](long long v, int c, double kp, const RP& x, double d) { emit(v, c, kp, combine(x), d); };
-    stencil_block3d<TX, TY, KZ, PF, NOPHI>(g, dinv, blockIdx.z, fetch, pre, combine, emit_raw);
+    stencil_block3d<TX, TY, KZ>(g, dinv, blockIdx.z, fetch, pre, combine, emit_raw);
   } else {
     pre();
     auto load = [&](long long v, int c) { return r[c * g.nn + v] + beta * pold[c * g.nn + v]; };
@@ -1307,7 +1228,6 @@ long long storage_edges(const GridArgs& g) {
   return (long long)g.nx * g.py * g.pz + (long long)g.px * g.ny * g.pz + (long long)g.px * g.py * g.nz;
 }
 
-int reduce_blocks(long long n) { return grid_1d(n, UPD_T, 1024); }
 
 void launch_mass(const GridArgs& g, const double* sigma_cell, double* mass, double* dinv, double* sqrtm,
                  hipStream_t s) {
@@ -1347,9 +1267,7 @@ struct TileShape {
 static const TileShape kSeedTiles[] = {{32, 4, 2}, {32, 4, 4}, {64, 2, 2}, {64, 2, 4}, {64, 4, 4},
                                        {64, 4, 8}, {32, 8, 4}, {32, 2, 2}, {64, 1, 4}, {64, 2, 8},
                                        {32, 4, 2}, {32, 4, 4}, {64, 2, 2}, {64, 4, 2}, {32, 8, 2}, {64, 2, 4},
-                                       {64, 4, 1}, {64, 8, 1}, {32, 8, 1}, {64, 2, 1},
-                                       // 20..23: no flux staging (20, 23: with prefetch; 21, 22: without)
-                                       {64, 8, 1}, {64, 8, 1}, {64, 4, 1}, {32, 8, 1}};
+                                       {64, 4, 1}, {64, 8, 1}, {32, 8, 1}, {64, 2, 1}};
 static int pick_seed_tile(const GridArgs& g) {
   // fixed per process (thread-safe static initialization); TEM_SEED_TILE overrides
   static const int v = [] {
@@ -1399,22 +1317,6 @@ void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold,
     TEM_SEED_CASE(17, 64, 8, 1)
     TEM_SEED_CASE(18, 32, 8, 1)
     TEM_SEED_CASE(19, 64, 2, 1)
-    case 20:
-      hipLaunchKernelGGL((k_seed_stencil<64, 8, 1, true, true, true, 4>), grid, block, 0, s, g, r, pold, pnew, q, dinv,
-                         s0, up, red.partials, st, local);
-      break;
-    case 21:
-      hipLaunchKernelGGL((k_seed_stencil<64, 8, 1, true, false, true, 6>), grid, block, 0, s, g, r, pold, pnew, q,
-                         dinv, s0, up, red.partials, st, local);
-      break;
-    case 22:
-      hipLaunchKernelGGL((k_seed_stencil<64, 4, 1, true, false, true, 8>), grid, block, 0, s, g, r, pold, pnew, q,
-                         dinv, s0, up, red.partials, st, local);
-      break;
-    case 23:
-      hipLaunchKernelGGL((k_seed_stencil<32, 8, 1, true, true, true, 4>), grid, block, 0, s, g, r, pold, pnew, q, dinv,
-                         s0, up, red.partials, st, local);
-      break;
   }
 #undef TEM_SEED_CASE
 }

@@ -96,3 +96,14 @@ def test_host_rkfit_matches_oracle_error_level():
     xi, c, err = T.poles(t, 38)
     o = R.rkfit(t, 38)
     assert 0.2 < err.max() / o["err"].max() < 5.0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus N > 1 exits with a message, before any
+    GPU work."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert p.returncode == 2 and "one GPU" in p.stderr

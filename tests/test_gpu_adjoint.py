@@ -84,10 +84,12 @@ def test_adjoint_two_sources_sum(tem):
 
 
 def test_adjoint_many_receivers_cocg_path(tem):
-    """More receivers than the per-receiver multi-shift path takes: the
-    batched COCG path gives the same gradient as the oracle."""
-    wl, s, C = _misfit_case(6, 16)
-    wl.receivers = [(i, j) for i in range(1, 6) for j in (1, 3, 5)][:14]
+    """More receivers (70) than the per-receiver multi-shift path takes (64):
+    the batched COCG path gives the same gradient as the oracle."""
+    wl = W.small_case(9, seed=9, t=W.log_channels(1e-5, 1e-3, 6))
+    wl.receivers = [(i, j) for i in range(9) for j in range(9)][:70]  # > 64: batched COCG
+    fit = rkfit.rkfit(wl.t, 16)
+    s, C = rkfit.shifts_and_coefficients(fit)
     P = yee.Problem(wl)
     rng = np.random.default_rng(5)
     w = rng.standard_normal((len(wl.t), len(wl.receivers)))
@@ -139,3 +141,24 @@ def test_adjoint_recomputes_solutions_when_not_kept(tem):
         ctx.solutions(0)
     g_re, st = ctx.adjoint(w)
     assert np.array_equal(g_keep, g_re)
+
+
+def test_adjoint_differentiation_config_16(tem):
+    """The differentiation workload at 16^3 (blocky current model, 30 surface
+    receivers, 40 channels, L2 misfit against the data of a blocky true
+    model): the GPU gradient matches the oracle's direct-solve gradient."""
+    true_wl, cur_wl = W.cfg_inverse(16)
+    fit = rkfit.rkfit(cur_wl.t, cur_wl.degree)
+    s, C = rkfit.shifts_and_coefficients(fit)
+    ctx = tem.Context.from_workload(true_wl)
+    d_obs, _ = ctx.forward(true_wl.loops, true_wl.receivers, -s, C)
+    ctx.set_conductivity(cur_wl.sigma)
+    d, st = ctx.forward(cur_wl.loops, cur_wl.receivers, -s, C, keep_solutions=True)
+    w = d - d_obs
+    g, sa = ctx.adjoint(w)
+    P = yee.Problem(cur_wl)
+    g_or = direct.misfit_gradient(P, s, C, w[0], method="banded")
+    err = np.linalg.norm(g.ravel() - g_or) / np.linalg.norm(g_or)
+    print("16^3 differentiation workload: %d receivers, adjoint rel err %.2e, %d + %d seed iterations"
+          % (len(cur_wl.receivers), err, st["iterations"], sa["iterations"]))
+    assert len(cur_wl.receivers) == 30 and err <= 1e-8
