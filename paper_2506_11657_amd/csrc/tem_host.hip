@@ -269,8 +269,9 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
   // One block of B seed iterations plus the deferred shift update is the same
   // launch sequence every time (slots depend on k mod B only), so it is
   // captured once per job into a HIP graph and replayed; with opts.profile,
-  // job 0 issues one block in kProfileEvery directly with an event pair around
-  // each launch (sampling the kernel times inside the timed solve).
+  // job 0 issues one block in kProfileEvery directly, each seed kernel's
+  // dispatch recording its own start and stop events (sampling the kernel
+  // times inside the timed solve).
   constexpr int kProfileEvery = 16;
   std::vector<hipEvent_t> ev;
   if (o.profile) {
@@ -289,12 +290,10 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
       double* rn = R + (size_t)((l + 1) % B) * n3;
       double* pold = pb + (size_t)((l + 1) & 1) * n3;
       double* pnew = pb + (size_t)(l & 1) * n3;
-      if (timed) (void)hipEventRecord(ev[4 * l], st);
-      tem::launch_seed_stencil(g, r, pold, pnew, q, ctx->d_dinv, s0, red, sl.d_state, l, st);
-      if (timed) (void)hipEventRecord(ev[4 * l + 1], st);
-      if (timed) (void)hipEventRecord(ev[4 * l + 2], st);
-      tem::launch_seed_update(g, r, q, rn, red, sl.d_state, l, st);
-      if (timed) (void)hipEventRecord(ev[4 * l + 3], st);
+      tem::launch_seed_stencil(g, r, pold, pnew, q, ctx->d_dinv, s0, red, sl.d_state, l, st,
+                               timed ? ev[4 * l] : nullptr, timed ? ev[4 * l + 1] : nullptr);
+      tem::launch_seed_update(g, r, q, rn, red, sl.d_state, l, st, timed ? ev[4 * l + 2] : nullptr,
+                              timed ? ev[4 * l + 3] : nullptr);
     }
     if (timed) (void)hipEventRecord(ev[4 * B], st);
     tem::launch_shift_block(g, J, red, sl.d_state, st);
@@ -334,7 +333,10 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     tem::launch_seed_init(g, (const double*)sl.gvec.p, (double*)sl.R.p, (double*)sl.pbuf.p + n3, Ys[i], (V*)sl.P.p,
                           J, red, sl.d_state, st);
     HIPCHK(ctx, hipGetLastError());
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    // Relaxed: another thread's context (a concurrent serving request) may
+    // allocate or free while this block is captured; a Global or ThreadLocal
+    // capture would make those calls fail in threads left in the default mode
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) == hipSuccess) {
       launch_block(i, false);
       hipError_t ce = hipStreamEndCapture(st, &run[i].graph);
       if (ce == hipSuccess) ce = hipGraphInstantiate(&run[i].exec, run[i].graph, nullptr, nullptr, 0);

@@ -98,10 +98,12 @@ void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double*
                       int J, Reduce red, SolveState* st, hipStream_t s);
 void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, float2* Y, float2* P,
                       int J, Reduce red, SolveState* st, hipStream_t s);
+// with t0 != nullptr the dispatch records its own start (t0) and stop (t1) events
 void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold, double* pnew, double* q,
-                         const double* dinv, double s0, Reduce red, SolveState* st, int local, hipStream_t s);
+                         const double* dinv, double s0, Reduce red, SolveState* st, int local, hipStream_t s,
+                         hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_seed_update(const GridArgs& g, const double* r, const double* q, double* rnext, Reduce red,
-                        SolveState* st, int local, hipStream_t s);
+                        SolveState* st, int local, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_block_update(const GridArgs& g, const double* R, double2* Y, double2* P, int J, int B,
                          const SolveState* st, hipStream_t s);
 void launch_block_update(const GridArgs& g, const double* R, float2* Y, float2* P, int J, int B,

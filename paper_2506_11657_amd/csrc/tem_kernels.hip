@@ -6,6 +6,9 @@
 //     (A + s_j) y_j = g,   A = M^{-1/2} K M^{-1/2},   g = M^{-1/2} f,
 // where K = C^T W C is applied matrix-free: face circulations of the scaled
 // field weighted by h_dual / (mu0 * area), then gathered back onto the edges.
+#include <hip/hip_ext.h>
+
+#include <cstdint>
 #include <cstdlib>
 
 #include "tem_internal.h"
@@ -1285,16 +1288,26 @@ static dim3 seed_stencil_grid(const GridArgs& g) {
   return dim3((g.nx + t.tx - 1) / t.tx, (g.ny + t.ty - 1) / t.ty, (g.nz + t.kz - 1) / t.kz);
 }
 
+// Launch on s; with t0 != nullptr the start and stop events are recorded by
+// the dispatch itself (the kernel's own execution interval, no extra packets).
+template <typename K, typename... A>
+static void launch_maybe_timed(K kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t s, hipEvent_t t0,
+                               hipEvent_t t1, A... args) {
+  if (t0) hipExtLaunchKernelGGL(kernel, grid, block, shm, s, t0, t1, 0u, args...);
+  else hipLaunchKernelGGL(kernel, grid, block, shm, s, args...);
+}
+
 void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold, double* pnew, double* q,
-                         const double* dinv, double s0, Reduce red, SolveState* st, int local, hipStream_t s) {
+                         const double* dinv, double s0, Reduce red, SolveState* st, int local, hipStream_t s,
+                         hipEvent_t t0, hipEvent_t t1) {
   const int v = pick_seed_tile(g);
   const TileShape t = kSeedTiles[v];
   const dim3 grid = seed_stencil_grid(g), block(t.tx, t.ty);
   const double* up = red.partials + kReduceSlots;
-#define TEM_SEED_CASE(I, X, Y, Z)                                                                          \
-  case I:                                                                                                  \
-    hipLaunchKernelGGL((k_seed_stencil<X, Y, Z, (I >= 10)>), grid, block, 0, s, g, r, pold, pnew, q, dinv, s0, up, \
-                       red.partials, st, local);                                                           \
+#define TEM_SEED_CASE(I, X, Y, Z)                                                                            \
+  case I:                                                                                                    \
+    launch_maybe_timed(k_seed_stencil<X, Y, Z, (I >= 10)>, grid, block, 0u, s, t0, t1, g, r, pold, pnew, q, dinv, \
+                       s0, up, red.partials, st, local);                                                     \
     break;
   switch (v) {
     TEM_SEED_CASE(0, 32, 4, 2)
@@ -1322,12 +1335,12 @@ void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold,
 }
 
 void launch_seed_update(const GridArgs& g, const double* r, const double* q, double* rnext, Reduce red,
-                        SolveState* st, int local, hipStream_t s) {
+                        SolveState* st, int local, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
   const long long n3 = 3 * g.nn;
   const dim3 sg = seed_stencil_grid(g);
   const int nst = sg.x * sg.y * sg.z;
-  hipLaunchKernelGGL(k_seed_update, dim3(UPD_BLOCKS), dim3(UPD_T), 0, s, n3, r, q, rnext, red.partials, nst,
-                     red.partials + kReduceSlots, st, local);
+  launch_maybe_timed(k_seed_update, dim3(UPD_BLOCKS), dim3(UPD_T), 0u, s, t0, t1, n3, r, q, rnext,
+                     (const double*)red.partials, nst, red.partials + kReduceSlots, st, local);
 }
 
 int seed_stencil_blocks(const GridArgs& g) {

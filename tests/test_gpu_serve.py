@@ -45,7 +45,8 @@ def test_alone_equals_mix_bitwise(tem):
     t0 = time.perf_counter()
     mix = mix_srv.run(reqs, realtime=True)
     summ = summarize(mix, time.perf_counter() - t0)
-    assert summ["completed"] == len(reqs)
+    errors = [(r.rid, r.error) for r in mix if r.error is not None]
+    assert summ["completed"] == len(reqs), errors
     for a, m in zip(alone, mix):
         assert a.error is None and m.error is None, (a.error, m.error)
         assert np.array_equal(a.data, m.data)
