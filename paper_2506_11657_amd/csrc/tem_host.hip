@@ -15,7 +15,9 @@
 
 using tem::GridArgs;
 using tem::SolveState;
-static_assert(sizeof(tem::SolveHead) <= 4096, "pinned head buffer");
+// the pinned head buffer holds two heads (two solver blocks in flight)
+constexpr size_t kHeadStride = 2048;
+static_assert(sizeof(tem::SolveHead) <= kHeadStride, "pinned head buffer");
 
 namespace {
 
@@ -47,9 +49,10 @@ constexpr int kMaxConcurrentSolves = 4;
 struct SolveSlot {
   DevBuf R, pbuf, q, partials, gvec, P, y32;  // ring, seed p (2), q, partial sums, g, per-shift p_j, FP32 y_j
   tem::SolveState* d_state = nullptr;
-  void* head = nullptr;          // pinned copy of the solver head
+  void* head = nullptr;          // pinned copies of the solver head, one per block in flight
   hipStream_t stream = nullptr;  // library-owned, default priority
   hipEvent_t ev = nullptr;       // orders the library stream after this slot
+  hipEvent_t head_ev[2] = {nullptr, nullptr};  // head copy of block b done (b mod 2)
 };
 
 }  // namespace
@@ -220,7 +223,8 @@ int ensure_slots(tem_ctx* ctx, int n) {
     HIPCHK(ctx, hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
     HIPCHK(ctx, hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
     HIPCHK(ctx, hipMalloc(&sl.d_state, sizeof(SolveState)));
-    HIPCHK(ctx, hipHostMalloc(&sl.head, 4096, hipHostMallocDefault));
+    HIPCHK(ctx, hipHostMalloc(&sl.head, 2 * kHeadStride, hipHostMallocDefault));
+    for (hipEvent_t& e : sl.head_ev) HIPCHK(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   return TEM_OK;
 }
@@ -230,6 +234,8 @@ void release_slot(SolveSlot& sl) {
   if (sl.d_state) (void)hipFree(sl.d_state);
   if (sl.head) (void)hipHostFree(sl.head);
   if (sl.ev) (void)hipEventDestroy(sl.ev);
+  for (hipEvent_t e : sl.head_ev)
+    if (e) (void)hipEventDestroy(e);
   if (sl.stream) (void)hipStreamDestroy(sl.stream);
 }
 
@@ -303,8 +309,12 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
   struct Run {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int k = 0;
+    int k = 0;             // seed iterations of the blocks whose head the host has read
+    int launched = 0;      // blocks issued
+    int checked = 0;       // blocks whose head the host has read
+    int sampled = -1;      // block issued with timing events
     bool done = false;
+    bool breakdown = false;
   };
   std::vector<Run> run(njobs);
   auto cleanup = [&]() {
@@ -352,37 +362,58 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
   }
   hipError_t lerr = hipSuccess;
   bool breakdown = false;
-  int nblock = 0;
   double next_report = 10.0;
+  // Issue block `launched` of job i: the graph (or direct launches when timed),
+  // then the copy of the head into pinned slot (launched mod 2) and its event.
+  auto issue = [&](int i) -> hipError_t {
+    SolveSlot& sl = ctx->slots[i];
+    Run& r = run[i];
+    const bool timed = o.profile && i == 0 && r.launched % kProfileEvery == 0;
+    hipError_t e = hipSuccess;
+    if (r.exec && !timed) e = hipGraphLaunch(r.exec, sl.stream);
+    else launch_block(i, timed);
+    if (e == hipSuccess) e = hipGetLastError();
+    const int h = r.launched & 1;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((char*)sl.head + h * kHeadStride, sl.d_state, sizeof(tem::SolveHead),
+                         hipMemcpyDeviceToHost, sl.stream);
+    if (e == hipSuccess) e = hipEventRecord(sl.head_ev[h], sl.stream);
+    if (timed) r.sampled = r.launched;
+    ++r.launched;
+    return e;
+  };
+  // Two blocks per job stay in flight: the host reads block b's head while
+  // block b+1 already runs, so the device never waits for the host between
+  // blocks.  A job that turns out converged at block b has issued block b+1
+  // as well; with every shift inactive that block changes no y_j (its shift
+  // update applies nothing), and its seed steps are not counted.
   for (;;) {
     bool any = false;
-    const bool sample = o.profile && (nblock++ % kProfileEvery == 0);
     for (int i = 0; i < njobs && lerr == hipSuccess; ++i) {
-      if (run[i].done) continue;
+      Run& r = run[i];
+      if (r.done) continue;
       any = true;
-      SolveSlot& sl = ctx->slots[i];
-      const bool timed = sample && i == 0;
-      if (run[i].exec && !timed) lerr = hipGraphLaunch(run[i].exec, sl.stream);
-      else launch_block(i, timed);
-      if (lerr == hipSuccess) lerr = hipGetLastError();
-      if (lerr == hipSuccess)
-        lerr = hipMemcpyAsync(sl.head, sl.d_state, sizeof(tem::SolveHead), hipMemcpyDeviceToHost, sl.stream);
+      while (lerr == hipSuccess && r.launched - r.checked < 2 && (long long)r.launched * B < o.max_iter)
+        lerr = issue(i);
     }
     if (!any || lerr != hipSuccess) break;
     int n_active_all = 0;
     for (int i = 0; i < njobs && lerr == hipSuccess; ++i) {
-      if (run[i].done) continue;
+      Run& r = run[i];
+      if (r.done) continue;
       SolveSlot& sl = ctx->slots[i];
-      lerr = hipStreamSynchronize(sl.stream);
+      const int h = r.checked & 1;
+      lerr = hipEventSynchronize(sl.head_ev[h]);
       if (lerr != hipSuccess) break;
-      run[i].k += B;
-      const tem::SolveHead head = *(const tem::SolveHead*)sl.head;
+      const tem::SolveHead head = *(const tem::SolveHead*)((const char*)sl.head + h * kHeadStride);
+      ++r.checked;
+      r.k = r.checked * B;
       int n_active = 0;
       for (int j = 0; j < J; ++j) n_active += head.active[j];
       n_active_all += n_active;
-      if (head.breakdown) breakdown = true;
-      if (head.breakdown || n_active == 0 || run[i].k >= o.max_iter) run[i].done = true;
-      if (sample && i == 0) {
+      if (head.breakdown) r.breakdown = breakdown = true;
+      if (head.breakdown || n_active == 0 || r.k >= o.max_iter) r.done = true;
+      if (r.sampled == r.checked - 1) {
         for (int l = 0; l < B; ++l) {
           float a = 0.f, b = 0.f;
           (void)hipEventElapsedTime(&a, ev[4 * l], ev[4 * l + 1]);
@@ -416,6 +447,10 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     SolveSlot& sl = ctx->slots[i];
     HIPCHK(ctx, hipMemcpyAsync(&states[i], sl.d_state, sizeof(SolveState), hipMemcpyDeviceToHost, sl.stream));
     HIPCHK(ctx, hipStreamSynchronize(sl.stream));
+    // the solve ended at the block the host last read; a block issued after it
+    // only advanced the seed
+    states[i].k = run[i].k;
+    states[i].breakdown = run[i].breakdown ? 1 : 0;
     // later work on the library stream reads Ys[i]
     HIPCHK(ctx, hipEventRecord(sl.ev, sl.stream));
     HIPCHK(ctx, hipStreamWaitEvent(ctx->work, sl.ev, 0));
