@@ -209,10 +209,9 @@ tem_solve_opts resolve_opts(const tem_solve_opts* o) {
 }
 
 int block_length(int requested, int J) {
-  // compiled block lengths; the coefficient table must fit in 64 KiB of LDS
-  int B = requested >= 64 ? 64 : requested >= 32 ? 32 : requested >= 16 ? 16 : 8;
-  while (B > 8 && (long long)J * (2 * B + 2) * 16 > 65536) B /= 2;
-  return B;
+  // the compiled block lengths
+  (void)J;
+  return requested >= 64 ? 64 : requested >= 32 ? 32 : requested >= 16 ? 16 : 8;
 }
 
 // Create solve slots 0..n-1 (stream, state, pinned head) if they do not exist.
@@ -267,7 +266,7 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     hs->z_re[j] = hs->zp_re[j] = 1.0;  // zeta_0 = zeta_{-1} = 1
     hs->active[j] = 1;
     hs->apply[j] = 1;
-    hs->a_re[j] = 1.0;
+    hs->cf[j][0][0] = 1.0;  // a = 1, c = 0: no update before the first block
   }
   HIPCHK(ctx, hipEventRecord(ctx->work_ev, ctx->work));
   auto t0 = std::chrono::steady_clock::now();
@@ -284,9 +283,8 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     ev.resize(2 * (2 * B + 1));
     for (auto& e : ev) HIPCHK(ctx, hipEventCreate(&e));
   }
-  auto launch_block = [&](int i, bool timed) {
+  auto launch_block = [&](int i, bool timed, tem::Sink& st) {
     SolveSlot& sl = ctx->slots[i];
-    hipStream_t st = sl.stream;
     double* R = (double*)sl.R.p;
     double* pb = (double*)sl.pbuf.p;
     double* q = (double*)sl.q.p;
@@ -301,10 +299,10 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
       tem::launch_seed_update(g, r, q, rn, red, sl.d_state, l, st, timed ? ev[4 * l + 2] : nullptr,
                               timed ? ev[4 * l + 3] : nullptr);
     }
-    if (timed) (void)hipEventRecord(ev[4 * B], st);
+    if (timed) (void)hipEventRecord(ev[4 * B], st.stream);
     tem::launch_shift_block(g, J, red, sl.d_state, st);
     tem::launch_block_update(g, R, Ys[i], (V*)sl.P.p, J, B, sl.d_state, st);
-    if (timed) (void)hipEventRecord(ev[4 * B + 1], st);
+    if (timed) (void)hipEventRecord(ev[4 * B + 1], st.stream);
   };
   struct Run {
     hipGraph_t graph = nullptr;
@@ -343,21 +341,25 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     tem::launch_seed_init(g, (const double*)sl.gvec.p, (double*)sl.R.p, (double*)sl.pbuf.p + n3, Ys[i], (V*)sl.P.p,
                           J, red, sl.d_state, st);
     HIPCHK(ctx, hipGetLastError());
-    // Relaxed: another thread's context (a concurrent serving request) may
-    // allocate or free while this block is captured; a Global or ThreadLocal
-    // capture would make those calls fail in threads left in the default mode
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) == hipSuccess) {
-      launch_block(i, false);
-      hipError_t ce = hipStreamEndCapture(st, &run[i].graph);
-      if (ce == hipSuccess) ce = hipGraphInstantiate(&run[i].exec, run[i].graph, nullptr, nullptr, 0);
-      if (ce != hipSuccess) {
-        (void)hipGetLastError();
-        if (run[i].graph) (void)hipGraphDestroy(run[i].graph);
-        run[i].graph = nullptr;
-        run[i].exec = nullptr;
-      }
-    } else {
+    // the block's kernels become the nodes of a graph built explicitly (no
+    // stream capture: a capture could be invalidated by a device-wide call such
+    // as hipFree from another request's thread); on failure the blocks are
+    // launched directly
+    tem::Sink gk;
+    hipError_t ge = hipGraphCreate(&run[i].graph, 0);
+    if (ge == hipSuccess) {
+      gk.graph = run[i].graph;
+      launch_block(i, false, gk);
+      ge = gk.err;
+    }
+    if (ge == hipSuccess) ge = hipGraphInstantiate(&run[i].exec, run[i].graph, nullptr, nullptr, 0);
+    if (ge != hipSuccess) {
       (void)hipGetLastError();
+      if (run[i].exec) (void)hipGraphExecDestroy(run[i].exec);
+      if (run[i].graph) (void)hipGraphDestroy(run[i].graph);
+      run[i].graph = nullptr;
+      run[i].exec = nullptr;
+      if (verbose()) fprintf(stderr, "[tem] solver block graph not built (%s): direct launches\n", hipGetErrorString(ge));
     }
   }
   hipError_t lerr = hipSuccess;
@@ -370,8 +372,13 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     Run& r = run[i];
     const bool timed = o.profile && i == 0 && r.launched % kProfileEvery == 0;
     hipError_t e = hipSuccess;
-    if (r.exec && !timed) e = hipGraphLaunch(r.exec, sl.stream);
-    else launch_block(i, timed);
+    if (r.exec && !timed) {
+      e = hipGraphLaunch(r.exec, sl.stream);
+    } else {
+      tem::Sink direct;
+      direct.stream = sl.stream;
+      launch_block(i, timed, direct);
+    }
     if (e == hipSuccess) e = hipGetLastError();
     const int h = r.launched & 1;
     if (e == hipSuccess)

@@ -56,11 +56,10 @@ struct SolveState {
   int apply[kMaxShifts];                            // updated at least once in this block
   int iters[kMaxShifts];
   double est[kMaxShifts];                           // |zeta| ||r|| at the stop
-  // block coefficients: p_new = a p + sum_l e_l r_l ; y_new = y + c p + sum_l d_l r_l
-  double a_re[kMaxShifts], a_im[kMaxShifts];
-  double c_re[kMaxShifts], c_im[kMaxShifts];
-  double d_re[kMaxShifts][kMaxBlock], d_im[kMaxShifts][kMaxBlock];
-  double e_re[kMaxShifts][kMaxBlock], e_im[kMaxShifts][kMaxBlock];
+  // block coefficients: p_new = a p + sum_l e_l r_l ; y_new = y + c p + sum_l d_l r_l,
+  // packed per shift for uniform reads: cf[j][0] = (a, c), cf[j][1 + l] = (e_l, d_l),
+  // each complex as (re, im)
+  double cf[kMaxShifts][kMaxBlock + 1][4];
 };
 
 struct SolveHead {  // the leading part of SolveState
@@ -89,6 +88,19 @@ struct Reduce {
   unsigned int* counter; // completion counters (zero between kernels)
 };
 
+// Destination of a solver-block launcher: with graph == nullptr the kernel is
+// launched on `stream` at once; otherwise it is appended to `graph` as a
+// kernel node depending on node `last` (explicit construction: no stream is
+// ever put in capture mode, so device-wide operations issued meanwhile by other
+// threads of the process, such as hipFree, cannot invalidate a capture).  The
+// first failing node addition is kept in err.
+struct Sink {
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphNode_t last = nullptr;
+  hipError_t err = hipSuccess;
+};
+
 // ---- launchers (tem_kernels.hip) -----------------------------------------
 void launch_mass(const GridArgs& g, const double* sigma_cell, double* mass, double* dinv, double* sqrtm,
                  hipStream_t s);
@@ -100,19 +112,19 @@ void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double*
                       int J, Reduce red, SolveState* st, hipStream_t s);
 // with t0 != nullptr the dispatch records its own start (t0) and stop (t1) events
 void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold, double* pnew, double* q,
-                         const double* dinv, double s0, Reduce red, SolveState* st, int local, hipStream_t s,
+                         const double* dinv, double s0, Reduce red, SolveState* st, int local, Sink& k,
                          hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_seed_update(const GridArgs& g, const double* r, const double* q, double* rnext, Reduce red,
-                        SolveState* st, int local, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+                        SolveState* st, int local, Sink& k, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_block_update(const GridArgs& g, const double* R, double2* Y, double2* P, int J, int B,
-                         const SolveState* st, hipStream_t s);
+                         const SolveState* st, Sink& k);
 void launch_block_update(const GridArgs& g, const double* R, float2* Y, float2* P, int J, int B,
-                         const SolveState* st, hipStream_t s);
+                         const SolveState* st, Sink& k);
 // J node-padded complex vectors, FP32 storage widened to FP64: sign 0 sets
 // Y_j = X_j for all j; sign +1 / -1 adds / subtracts X_j for the j in mask
 void launch_accumulate(const GridArgs& g, int J, const float2* X, double2* Y, int sign, unsigned long long mask,
                        hipStream_t s);
-void launch_shift_block(const GridArgs& g, int J, Reduce red, SolveState* st, hipStream_t s);
+void launch_shift_block(const GridArgs& g, int J, Reduce red, SolveState* st, Sink& k);
 void launch_cstencil(const GridArgs& g, const double2* X, long long xstride, const double* dinv,
                      const double* shift_re, const double* shift_im, int nvec, const double2* rhs,
                      double2* out, long long ostride, double* norm_partials, hipStream_t s);

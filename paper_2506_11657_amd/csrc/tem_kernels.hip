@@ -9,6 +9,7 @@
 #include <hip/hip_ext.h>
 
 #include <cstdint>
+#include <tuple>
 #include <cstdlib>
 
 #include "tem_internal.h"
@@ -592,17 +593,19 @@ __global__ void __launch_bounds__(64) k_shift_block(const double* __restrict__ u
     if (est2 <= tol2) active = false;
   }
   if (lane < B) {
-    st->d_re[j][lane] = d.re;
-    st->d_im[j][lane] = d.im;
-    st->e_re[j][lane] = e.re;
-    st->e_im[j][lane] = e.im;
+    double* cl = st->cf[j][1 + lane];
+    cl[0] = e.re;
+    cl[1] = e.im;
+    cl[2] = d.re;
+    cl[3] = d.im;
   }
   if (lane == 0) {
     st->apply[j] = 1;
-    st->a_re[j] = a.re;
-    st->a_im[j] = a.im;
-    st->c_re[j] = c.re;
-    st->c_im[j] = c.im;
+    double* c0 = st->cf[j][0];
+    c0[0] = a.re;
+    c0[1] = a.im;
+    c0[2] = c.re;
+    c0[3] = c.im;
     st->z_re[j] = z.re;
     st->z_im[j] = z.im;
     st->zp_re[j] = zp.re;
@@ -616,34 +619,23 @@ __global__ void __launch_bounds__(64) k_shift_block(const double* __restrict__ u
 
 // Deferred shift update after a block of BB seed iterations:
 //   p_j <- a_j p_j + sum_l e_jl r_l,   y_j <- y_j + c_j p_j + sum_l d_jl r_l
-// for every shift updated in the block (coefficients from k_seed_update).
-// Coefficients sit in shared memory, (a, c, e_0.., d_0..) per shift.
+// for every shift updated in the block (coefficients from k_shift_block).
+// The coefficients are the same for every thread, so they are read with
+// uniform loads from the state (scalar registers as FMA operands) rather than
+// staged through LDS, whose broadcast reads stalled the waves; the kernel
+// writes nothing the coefficients could alias.
 constexpr int BU_T = 256;
 template <int BB, typename V>
-__global__ void __launch_bounds__(BU_T) k_block_update(long long n3, const double* __restrict__ R, V* Y, V* P, int J,
-                                                       const SolveState* st) {
-  extern __shared__ double cf[];
-  __shared__ int app[kMaxShifts];
-  constexpr int W = 2 * BB + 2;
-  for (int idx = threadIdx.x; idx < J * W; idx += BU_T) {
-    const int j = idx / W, m = idx % W;
-    double re, im;
-    if (m == 0) { re = st->a_re[j]; im = st->a_im[j]; }
-    else if (m == 1) { re = st->c_re[j]; im = st->c_im[j]; }
-    else if (m < 2 + BB) { re = st->e_re[j][m - 2]; im = st->e_im[j][m - 2]; }
-    else { re = st->d_re[j][m - 2 - BB]; im = st->d_im[j][m - 2 - BB]; }
-    cf[2 * idx] = re;
-    cf[2 * idx + 1] = im;
-  }
-  for (int j = threadIdx.x; j < J; j += BU_T) app[j] = st->apply[j];
-  __syncthreads();
+__global__ void __launch_bounds__(BU_T) k_block_update(long long n3, const double* __restrict__ R, V* __restrict__ Y,
+                                                       V* __restrict__ P, int J,
+                                                       const SolveState* __restrict__ st) {
   for (long long e = blockIdx.x * (long long)BU_T + threadIdx.x; e < n3; e += (long long)gridDim.x * BU_T) {
     double rl[BB];
 #pragma unroll
     for (int l = 0; l < BB; ++l) rl[l] = R[(long long)l * n3 + e];
     for (int j = 0; j < J; ++j) {
-      if (!app[j]) continue;
-      const double* c = cf + 2 * j * W;
+      if (!st->apply[j]) continue;
+      const double* c = st->cf[j][0];
       const cplx p = ldv(P, (long long)j * n3 + e);
       const cplx y = ldv(Y, (long long)j * n3 + e);
       double pr = c[0] * p.re - c[1] * p.im;
@@ -652,10 +644,11 @@ __global__ void __launch_bounds__(BU_T) k_block_update(long long n3, const doubl
       double yi = y.im + c[2] * p.im + c[3] * p.re;
 #pragma unroll
       for (int l = 0; l < BB; ++l) {
-        pr += c[4 + 2 * l] * rl[l];
-        pi += c[5 + 2 * l] * rl[l];
-        yr += c[4 + 2 * BB + 2 * l] * rl[l];
-        yi += c[5 + 2 * BB + 2 * l] * rl[l];
+        const double* cl = c + 4 * (l + 1);
+        pr += cl[0] * rl[l];
+        pi += cl[1] * rl[l];
+        yr += cl[2] * rl[l];
+        yi += cl[3] * rl[l];
       }
       stv(P, (long long)j * n3 + e, cplx{pr, pi});
       stv(Y, (long long)j * n3 + e, cplx{yr, yi});
@@ -1288,17 +1281,42 @@ static dim3 seed_stencil_grid(const GridArgs& g) {
   return dim3((g.nx + t.tx - 1) / t.tx, (g.ny + t.ty - 1) / t.ty, (g.nz + t.kz - 1) / t.kz);
 }
 
-// Launch on s; with t0 != nullptr the start and stop events are recorded by
-// the dispatch itself (the kernel's own execution interval, no extra packets).
-template <typename K, typename... A>
-static void launch_maybe_timed(K kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t s, hipEvent_t t0,
-                               hipEvent_t t1, A... args) {
-  if (t0) hipExtLaunchKernelGGL(kernel, grid, block, shm, s, t0, t1, 0u, args...);
-  else hipLaunchKernelGGL(kernel, grid, block, shm, s, args...);
+// Put one kernel into k: a launch on k.stream (with t0 != nullptr the
+// dispatch itself records its start and stop events, the kernel's own
+// execution interval with no extra packets), or a kernel node of k.graph after
+// k.last.  The arguments are converted to the kernel's parameter types first;
+// both the launch and the node take copies of them.
+template <typename... P, typename... A>
+static void put(Sink& k, void (*kernel)(P...), dim3 grid, dim3 block, uint32_t shm, hipEvent_t t0, hipEvent_t t1,
+                A... args) {
+  static_assert(sizeof...(P) == sizeof...(A), "kernel argument count");
+  std::tuple<P...> vals(args...);
+  void* params[sizeof...(P)];
+  std::apply([&](auto&... v) {
+    int i = 0;
+    ((params[i++] = (void*)&v), ...);
+  }, vals);
+  void* fn = reinterpret_cast<void*>(kernel);
+  if (!k.graph) {
+    if (t0) hipExtLaunchKernel(fn, grid, block, params, shm, k.stream, t0, t1, 0);
+    else hipLaunchKernel(fn, grid, block, params, shm, k.stream);
+    return;
+  }
+  if (k.err != hipSuccess) return;
+  hipKernelNodeParams np{};
+  np.func = fn;
+  np.gridDim = grid;
+  np.blockDim = block;
+  np.sharedMemBytes = shm;
+  np.kernelParams = params;
+  np.extra = nullptr;
+  hipGraphNode_t node = nullptr;
+  k.err = hipGraphAddKernelNode(&node, k.graph, k.last ? &k.last : nullptr, k.last ? 1 : 0, &np);
+  if (k.err == hipSuccess) k.last = node;
 }
 
 void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold, double* pnew, double* q,
-                         const double* dinv, double s0, Reduce red, SolveState* st, int local, hipStream_t s,
+                         const double* dinv, double s0, Reduce red, SolveState* st, int local, Sink& k,
                          hipEvent_t t0, hipEvent_t t1) {
   const int v = pick_seed_tile(g);
   const TileShape t = kSeedTiles[v];
@@ -1306,8 +1324,8 @@ void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold,
   const double* up = red.partials + kReduceSlots;
 #define TEM_SEED_CASE(I, X, Y, Z)                                                                            \
   case I:                                                                                                    \
-    launch_maybe_timed(k_seed_stencil<X, Y, Z, (I >= 10)>, grid, block, 0u, s, t0, t1, g, r, pold, pnew, q, dinv, \
-                       s0, up, red.partials, st, local);                                                     \
+    put(k, k_seed_stencil<X, Y, Z, (I >= 10)>, grid, block, 0u, t0, t1, g, r, pold, pnew, q, dinv, s0, up,      \
+        red.partials, st, local);                                                                            \
     break;
   switch (v) {
     TEM_SEED_CASE(0, 32, 4, 2)
@@ -1335,12 +1353,12 @@ void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold,
 }
 
 void launch_seed_update(const GridArgs& g, const double* r, const double* q, double* rnext, Reduce red,
-                        SolveState* st, int local, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+                        SolveState* st, int local, Sink& k, hipEvent_t t0, hipEvent_t t1) {
   const long long n3 = 3 * g.nn;
   const dim3 sg = seed_stencil_grid(g);
   const int nst = sg.x * sg.y * sg.z;
-  launch_maybe_timed(k_seed_update, dim3(UPD_BLOCKS), dim3(UPD_T), 0u, s, t0, t1, n3, r, q, rnext,
-                     (const double*)red.partials, nst, red.partials + kReduceSlots, st, local);
+  put(k, k_seed_update, dim3(UPD_BLOCKS), dim3(UPD_T), 0u, t0, t1, n3, r, q, rnext, (const double*)red.partials, nst,
+      red.partials + kReduceSlots, st, local);
 }
 
 int seed_stencil_blocks(const GridArgs& g) {
@@ -1348,32 +1366,31 @@ int seed_stencil_blocks(const GridArgs& g) {
   return sg.x * sg.y * sg.z;
 }
 
-void launch_shift_block(const GridArgs& g, int J, Reduce red, SolveState* st, hipStream_t s) {
+void launch_shift_block(const GridArgs& g, int J, Reduce red, SolveState* st, Sink& k) {
   (void)g;
-  hipLaunchKernelGGL(k_shift_block, dim3(J), dim3(64), 0, s, (const double*)(red.partials + kReduceSlots), st);
+  put(k, k_shift_block, dim3(J), dim3(64), 0u, nullptr, nullptr, (const double*)(red.partials + kReduceSlots), st);
 }
 
 
 template <typename V>
 static void block_update(const GridArgs& g, const double* R, V* Y, V* P, int J, int B, const SolveState* st,
-                         hipStream_t s) {
+                         Sink& k) {
   const long long n3 = 3 * g.nn;
   const dim3 grid(grid_1d(n3, BU_T, 4096)), block(BU_T);
-  const size_t shm = (size_t)J * (2 * B + 2) * 2 * sizeof(double);
   switch (B) {
-    case 16: hipLaunchKernelGGL((k_block_update<16, V>), grid, block, shm, s, n3, R, Y, P, J, st); break;
-    case 32: hipLaunchKernelGGL((k_block_update<32, V>), grid, block, shm, s, n3, R, Y, P, J, st); break;
-    case 64: hipLaunchKernelGGL((k_block_update<64, V>), grid, block, shm, s, n3, R, Y, P, J, st); break;
-    default: hipLaunchKernelGGL((k_block_update<8, V>), grid, block, shm, s, n3, R, Y, P, J, st); break;
+    case 16: put(k, k_block_update<16, V>, grid, block, 0u, nullptr, nullptr, n3, R, Y, P, J, st); break;
+    case 32: put(k, k_block_update<32, V>, grid, block, 0u, nullptr, nullptr, n3, R, Y, P, J, st); break;
+    case 64: put(k, k_block_update<64, V>, grid, block, 0u, nullptr, nullptr, n3, R, Y, P, J, st); break;
+    default: put(k, k_block_update<8, V>, grid, block, 0u, nullptr, nullptr, n3, R, Y, P, J, st); break;
   }
 }
 void launch_block_update(const GridArgs& g, const double* R, double2* Y, double2* P, int J, int B,
-                         const SolveState* st, hipStream_t s) {
-  block_update(g, R, Y, P, J, B, st, s);
+                         const SolveState* st, Sink& k) {
+  block_update(g, R, Y, P, J, B, st, k);
 }
 void launch_block_update(const GridArgs& g, const double* R, float2* Y, float2* P, int J, int B,
-                         const SolveState* st, hipStream_t s) {
-  block_update(g, R, Y, P, J, B, st, s);
+                         const SolveState* st, Sink& k) {
+  block_update(g, R, Y, P, J, B, st, k);
 }
 
 void launch_accumulate(const GridArgs& g, int J, const float2* X, double2* Y, int sign, unsigned long long mask,

@@ -192,8 +192,8 @@ def test_noconv_and_errors(tem):
 
 
 def test_max_shifts_and_channels_no_receivers(tem):
-    """J = 64 shifts (the maximum; the coefficient table forces 16-iteration
-    blocks) and T = 64 channels with no receivers (fields only): every shift
+    """J = 64 shifts (the maximum) and T = 64 channels with no receivers
+    (fields only), at the default 64-iteration blocks: every shift
     matches the banded direct solve and the fields equal Re(X C)."""
     import torch
     wl = W.small_case(6, seed=8, t=W.log_channels(1e-5, 1e-3, 64))
