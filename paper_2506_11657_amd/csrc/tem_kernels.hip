@@ -36,6 +36,15 @@ __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
   double r = b.re / b.im, den = b.re * r + b.im;
   return {(a.re * r + a.im) / den, (a.im * r - a.re) / den};
 }
+// 1/b with the same scaling as Smith's quotient: two real divisions
+__device__ __forceinline__ cplx crecip(cplx b) {
+  if (fabs(b.re) >= fabs(b.im)) {
+    const double r = b.im / b.re, t = 1.0 / (b.re + b.im * r);
+    return {t, -r * t};
+  }
+  const double r = b.re / b.im, t = 1.0 / (b.re * r + b.im);
+  return {r * t, -t};
+}
 // Complex vectors are stored as double2 (FP64 path) or float2 (complex FP32
 // storage of precision 1); arithmetic is always in double.
 __device__ __forceinline__ cplx ldv(const double2* p, long long i) {
@@ -406,6 +415,14 @@ constexpr int UPD_PF = 4;        // elements per thread loaded ahead of the upda
 
 // Fixed-order sum of n partials written by the previous kernel (every block
 // of the reading kernel computes the same value; no inter-block traffic).
+// v as held by lane l of the wavefront (l the same in every lane)
+__device__ inline double from_lane(double v, int l) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)bits, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ double sum_prev(const double* __restrict__ partials, int n, double* lds) {
   double s = 0.0;
   for (int i = flat_tid(); i < n; i += flat_threads()) s += partials[i];
@@ -562,17 +579,28 @@ __global__ void __launch_bounds__(64) k_shift_block(const double* __restrict__ u
   int iters = st->iters[j];
   bool active = true, bad = false;
   double est = st->est[j];
+  // the block's history, slot `lane` in lane `lane`, fetched in one round
+  // trip; each step below takes its scalars from a lane instead of waiting on
+  // memory (the state was written by other kernels, so every such read would
+  // miss the caches)
+  const double h_alpha = lane < B ? st->alpha_h[lane] : 0.0;
+  const double h_beta = lane < B - 1 ? st->beta_h[lane] : beta_last;
+  const double h_rr = lane < B - 1 ? st->rr_h[lane] : rr_last;
+  const double carry_alpha = st->carry_alpha, carry_beta = st->carry_beta;
   for (int i = 0; i < B && active; ++i) {
-    const double a_k = st->alpha_h[i];
-    const double b_k = i == B - 1 ? beta_last : st->beta_h[i];
-    const double rr_next = i == B - 1 ? rr_last : st->rr_h[i];
-    const double a_km1 = i ? st->alpha_h[i - 1] : st->carry_alpha;
-    const double b_km1 = i ? st->beta_h[i - 1] : st->carry_beta;
+    const double a_k = from_lane(h_alpha, i);
+    const double b_k = from_lane(h_beta, i);
+    const double rr_next = from_lane(h_rr, i);
+    const double a_km1 = i ? from_lane(h_alpha, i - 1) : carry_alpha;
+    const double b_km1 = i ? from_lane(h_beta, i - 1) : carry_beta;
     const cplx num = a_km1 * cmul(z, zp);
     const cplx one_sa{1.0 + sig.re * a_k, sig.im * a_k};
     const cplx den = (a_k * b_km1) * (zp - z) + a_km1 * cmul(zp, one_sa);
-    const cplx zn = cdiv(num, den);
-    const cplx ratio = cdiv(zn, z);
+    // zeta_{k+1} / zeta_k = a_{k-1} zeta_{k-1} / den: one reciprocal serves both
+    // (divisions are the longest latency chain of this single-wave recurrence)
+    const cplx inv = crecip(den);
+    const cplx zn = cmul(num, inv);
+    const cplx ratio = a_km1 * cmul(zp, inv);
     const cplx as = a_k * ratio;
     const cplx bs = b_k * cmul(ratio, ratio);
     if (!(isfinite(zn.re) && isfinite(zn.im) && isfinite(as.re) && isfinite(as.im) && isfinite(bs.re) &&
@@ -1298,8 +1326,8 @@ static void put(Sink& k, void (*kernel)(P...), dim3 grid, dim3 block, uint32_t s
   }, vals);
   void* fn = reinterpret_cast<void*>(kernel);
   if (!k.graph) {
-    if (t0) hipExtLaunchKernel(fn, grid, block, params, shm, k.stream, t0, t1, 0);
-    else hipLaunchKernel(fn, grid, block, params, shm, k.stream);
+    if (t0) (void)hipExtLaunchKernel(fn, grid, block, params, shm, k.stream, t0, t1, 0);
+    else (void)hipLaunchKernel(fn, grid, block, params, shm, k.stream);
     return;
   }
   if (k.err != hipSuccess) return;
