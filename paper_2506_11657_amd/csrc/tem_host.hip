@@ -273,7 +273,7 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
 
   // One block of B seed iterations plus the deferred shift update is the same
   // launch sequence every time (slots depend on k mod B only), so it is
-  // captured once per job into a HIP graph and replayed; with opts.profile,
+  // built once per job as a HIP graph and replayed; with opts.profile,
   // job 0 issues one block in kProfileEvery directly, each seed kernel's
   // dispatch recording its own start and stop events (sampling the kernel
   // times inside the timed solve).
