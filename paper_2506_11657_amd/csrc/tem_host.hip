@@ -334,13 +334,21 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     }
     // buffers allocated above are cleared on the library stream; the slot's
     // work starts after that and after its right-hand side
-    HIPCHK(ctx, hipEventRecord(ctx->work_ev, ctx->work));
-    HIPCHK(ctx, hipStreamWaitEvent(st, ctx->work_ev, 0));
-    HIPCHK(ctx, hipMemcpyAsync(sl.d_state, hs.get(), sizeof(SolveState), hipMemcpyHostToDevice, st));
-    const tem::Reduce red{(double*)sl.partials.p, ctx->d_counters};
-    tem::launch_seed_init(g, (const double*)sl.gvec.p, (double*)sl.R.p, (double*)sl.pbuf.p + n3, Ys[i], (V*)sl.P.p,
-                          J, red, sl.d_state, st);
-    HIPCHK(ctx, hipGetLastError());
+    hipError_t se = hipEventRecord(ctx->work_ev, ctx->work);
+    if (se == hipSuccess) se = hipStreamWaitEvent(st, ctx->work_ev, 0);
+    if (se == hipSuccess)
+      se = hipMemcpyAsync(sl.d_state, hs.get(), sizeof(SolveState), hipMemcpyHostToDevice, st);
+    if (se == hipSuccess) {
+      const tem::Reduce red{(double*)sl.partials.p, ctx->d_counters};
+      tem::launch_seed_init(g, (const double*)sl.gvec.p, (double*)sl.R.p, (double*)sl.pbuf.p + n3, Ys[i],
+                            (V*)sl.P.p, J, red, sl.d_state, st);
+      se = hipGetLastError();
+    }
+    if (se != hipSuccess) {
+      for (int m = 0; m <= i; ++m) (void)hipStreamSynchronize(ctx->slots[m].stream);
+      cleanup();
+      return fail(ctx, TEM_EHIP, std::string("solver set-up: ") + hipGetErrorString(se));
+    }
     // the block's kernels become the nodes of a graph built explicitly (no
     // stream capture: a capture could be invalidated by a device-wide call such
     // as hipFree from another request's thread); on failure the blocks are
@@ -446,23 +454,30 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     }
   }
   if (lerr != hipSuccess) {
+    // blocks still in flight finish before their graphs and events are destroyed
+    for (int i = 0; i < njobs; ++i) (void)hipStreamSynchronize(ctx->slots[i].stream);
     cleanup();
     return fail(ctx, TEM_EHIP, std::string("solver loop: ") + hipGetErrorString(lerr));
   }
   seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  hipError_t fe = hipSuccess;
   for (int i = 0; i < njobs; ++i) {
     SolveSlot& sl = ctx->slots[i];
-    HIPCHK(ctx, hipMemcpyAsync(&states[i], sl.d_state, sizeof(SolveState), hipMemcpyDeviceToHost, sl.stream));
-    HIPCHK(ctx, hipStreamSynchronize(sl.stream));
+    if (fe == hipSuccess)
+      fe = hipMemcpyAsync(&states[i], sl.d_state, sizeof(SolveState), hipMemcpyDeviceToHost, sl.stream);
+    // also waits for a block issued after the last one the host read
+    const hipError_t se = hipStreamSynchronize(sl.stream);
+    if (fe == hipSuccess) fe = se;
     // the solve ended at the block the host last read; a block issued after it
     // only advanced the seed
     states[i].k = run[i].k;
     states[i].breakdown = run[i].breakdown ? 1 : 0;
     // later work on the library stream reads Ys[i]
-    HIPCHK(ctx, hipEventRecord(sl.ev, sl.stream));
-    HIPCHK(ctx, hipStreamWaitEvent(ctx->work, sl.ev, 0));
+    if (fe == hipSuccess) fe = hipEventRecord(sl.ev, sl.stream);
+    if (fe == hipSuccess) fe = hipStreamWaitEvent(ctx->work, sl.ev, 0);
   }
   cleanup();
+  if (fe != hipSuccess) return fail(ctx, TEM_EHIP, std::string("solver end: ") + hipGetErrorString(fe));
   for (int i = 0; i < njobs; ++i) breakdown |= states[i].breakdown != 0;
   if (breakdown) return fail(ctx, TEM_EBREAKDOWN, "Krylov breakdown in the shared recurrence");
   for (int i = 0; i < njobs; ++i)
