@@ -409,8 +409,8 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
 }
 
 constexpr int STX = 32, STY = 4, SKZ = 2;
-constexpr int UPD_T = 1024;      // threads per block of the seed update and init
-constexpr int UPD_BLOCKS = 256;  // blocks of the seed update (= partials it leaves)
+constexpr int UPD_T = 512;       // threads per block of the seed update and init
+constexpr int UPD_BLOCKS = 512;  // blocks of the seed update (= partials it leaves)
 constexpr int UPD_PF = 4;        // elements per thread loaded ahead of the update's reduction
 
 // Fixed-order sum of n partials written by the previous kernel (every block
