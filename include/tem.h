@@ -89,8 +89,7 @@ typedef struct {
                         ||g - (A + s_j) y_j||_2 <= rtol ||g||_2 (<= 0 selects 3e-8) */
   int max_iter;      /* cap on seed iterations per solve; <= 0 selects 2000000 */
   int block;         /* iterations between deferred shift updates (8, 16, 32 or 64; other
-                        values round down, and J (2 block + 2) 16 bytes must fit in 64 KiB);
-                        <= 0 selects 64 */
+                        values round down); <= 0 selects 64 */
   double seed_shift; /* real seed shift of the shared recurrence; <= 0 selects
                         max(min_j Re s_j, 1e-3 min_j |s_j|), s_j = -xi_j */
   int refine_max;    /* precision 1: cap on refinement passes; <= 0 selects 8; a shift

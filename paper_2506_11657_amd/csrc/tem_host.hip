@@ -208,9 +208,8 @@ tem_solve_opts resolve_opts(const tem_solve_opts* o) {
   return r;
 }
 
-int block_length(int requested, int J) {
-  // the compiled block lengths
-  (void)J;
+// the compiled block lengths
+int block_length(int requested) {
   return requested >= 64 ? 64 : requested >= 32 ? 32 : requested >= 16 ? 16 : 8;
 }
 
@@ -250,7 +249,7 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
                      double s0, const tem_solve_opts& o, int njobs, V* const* Ys, SolveState* states,
                      double& seconds) {
   const int J = (int)shifts_re.size();
-  const int B = block_length(o.block, J);
+  const int B = block_length(o.block);
   const GridArgs& g = ctx->g;
   const size_t n3 = ctx->n3;
   int rc;
