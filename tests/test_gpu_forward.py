@@ -157,6 +157,26 @@ def test_bitwise_repeatable(tem):
     assert np.array_equal(d1, d2) and np.array_equal(X1, X2)
 
 
+def test_graph_and_direct_launches_agree_bitwise(tem):
+    """With profile=True every 16th solver block is issued as direct kernel
+    launches with per-dispatch events instead of a graph replay: the same
+    kernels in the same order, so data and solutions are bitwise equal; the
+    sampled kernel times are reported; and a converged solve reports the
+    iterations of the blocks it checked (a multiple of the block length)."""
+    wl = W.small_case(8, seed=9, t=W.log_channels(1e-5, 1e-3, 8))
+    xi, s, C = _fit(wl.t, 16)
+    ctx = tem.Context.from_workload(wl)
+    d1, st1 = ctx.forward(wl.loops, wl.receivers, xi, C, keep_solutions=True)
+    X1 = ctx.solutions(0)
+    d2, st2 = ctx.forward(wl.loops, wl.receivers, xi, C, keep_solutions=True, profile=True)
+    X2 = ctx.solutions(0)
+    print("iterations %d, sampled stencil launches %d" % (st2["iterations"], st2["kernel_launches"][0]))
+    assert np.array_equal(d1, d2) and np.array_equal(X1, X2)
+    assert st1["iterations"] == st2["iterations"] and st1["iterations"] % 64 == 0
+    assert st2["kernel_launches"][0] > 0 and st2["kernel_ms"][0] > 0.0
+    assert st1["kernel_launches"][0] == 0
+
+
 def test_block_length_does_not_change_result(tem):
     """Deferred shift updates every B iterations are the same recurrence: B = 8,
     16, 32, 64 agree to rounding."""
