@@ -25,6 +25,9 @@ struct GridArgs {
   int nx, ny, nz;
   int px, py, pz;
   long long nn;             // px * py * pz
+  // one allocation of nine arrays of L = max_a n_a + 1 entries: axis a has
+  // h[a] = h[0] + 3 a L, ih[a] = h[a] + L, dw[a] = h[a] + 2 L (the seed stencil
+  // relies on this layout)
   const double* h[3];       // widths, length n_a + 1 (last entry 0)
   const double* ih[3];      // 1 / width, last entry 0
   const double* dw[3];      // dual width / mu0 per node, length n_a + 1

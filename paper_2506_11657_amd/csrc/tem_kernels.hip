@@ -72,6 +72,34 @@ __device__ __forceinline__ int flat_threads() { return blockDim.x * blockDim.y *
 
 // Deterministic block sum (wave64 shuffles, then the waves in fixed order);
 // the result is valid in thread 0.  lds needs one double per wave.
+// The same two reductions for a block of NT threads known at compile time
+// (thread index tid): no read of the block size from the dispatch packet.
+// block_sum_n leaves the sum in thread 0; block_total_n gives it to every
+// thread (each sums the wave totals in the same fixed order).
+template <int NT>
+__device__ __forceinline__ double block_sum_n(double v, double* lds, int tid) {
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
+  const int lane = tid % kWave, wid = tid / kWave;
+  __syncthreads();
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (tid == 0)
+    for (int w = 0; w < (NT + kWave - 1) / kWave; ++w) s += lds[w];
+  return s;
+}
+template <int NT>
+__device__ __forceinline__ double block_total_n(double v, double* lds, int tid) {
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
+  const int lane = tid % kWave, wid = tid / kWave;
+  __syncthreads();
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (NT + kWave - 1) / kWave; ++w) s += lds[w];
+  return s;
+}
+
 __device__ double block_sum(double v, double* lds) {
   for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
   const int tid = flat_tid();
@@ -333,29 +361,52 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
       hr[l][c] = in ? fetch(v, c) : Raw{};
     }
   }
-  for (int e = tid; e < (TX + 1) + (TY + 1) + (KZ + 1); e += NT) {
-    if (e < TX + 1) {
-      const int gi = i0 - 1 + e;
-      const bool ok = gi >= 0 && gi <= g.nx;
-      wxh[e] = ok ? g.h[0][gi] : 0.0;
-      wxi[e] = ok ? g.ih[0][gi] : 0.0;
-      wxd[e] = ok ? g.dw[0][gi] : 0.0;
-    } else if (e < (TX + 1) + (TY + 1)) {
-      const int q = e - (TX + 1), gj = j0 - 1 + q;
-      const bool ok = gj >= 0 && gj <= g.ny;
-      wyh[q] = ok ? g.h[1][gj] : 0.0;
-      wyi[q] = ok ? g.ih[1][gj] : 0.0;
-      wyd[q] = ok ? g.dw[1][gj] : 0.0;
-    } else {
-      const int q = e - (TX + 1) - (TY + 1), kk = k0 - 1 + q;
-      const bool ok = kk >= 0 && kk <= g.nz;
-      wzh[q] = ok ? g.h[2][kk] : 0.0;
-      wzi[q] = ok ? g.ih[2][kk] : 0.0;
-      wzd[q] = ok ? g.dw[2][kk] : 0.0;
-    }
+  // 1-D weights of the block's flux nodes: entries (TX + 1) + (TY + 1) + (KZ + 1),
+  // loaded into registers now, stored to LDS only after pre() (a store would
+  // wait for every load issued before it)
+  constexpr int NWE = (TX + 1) + (TY + 1) + (KZ + 1);
+  constexpr int NW = (NWE + NT - 1) / NT;
+  double wv[NW][3];
+  // branch-free (selected pointers, clamped index): a load under a branch
+  // would be waited for inside it
+  bool wok[NW];
+#pragma unroll
+  for (int m = 0; m < NW; ++m) {
+    const int e = tid + m * NT;
+    const bool onx = e < TX + 1, ony = !onx && e < (TX + 1) + (TY + 1);
+    const int gi = onx ? i0 - 1 + e : ony ? j0 - 1 + (e - (TX + 1)) : k0 - 1 + (e - (TX + 1) - (TY + 1));
+    const int hi = onx ? g.nx : ony ? g.ny : g.nz;
+    wok[m] = e < NWE && gi >= 0 && gi <= hi;
+    // the nine axis arrays are one allocation, axis a at h[0] + 3 a L with
+    // h, 1/h and dual widths L apart (a pointer chosen per lane would put the
+    // argument block in scratch)
+    const long long L = g.ih[0] - g.h[0];
+    const double* b = g.h[0] + 3 * (onx ? 0 : ony ? 1 : 2) * L + (wok[m] ? gi : 0);
+    wv[m][0] = b[0];
+    wv[m][1] = b[L];
+    wv[m][2] = b[2 * L];
   }
+  // the owner's widths for the edges it emits (clamped for threads that own none)
+  const double ohx = g.h[0][min(i, g.nx)], ohy = g.h[1][min(j, g.ny)];
+  double ohz[KZ];
+#pragma unroll
+  for (int z = 0; z < KZ; ++z) ohz[z] = g.h[2][min(k0 + z, g.nz)];
   // 2. the caller's reduction overlaps the loads above
   pre();
+#pragma unroll
+  for (int m = 0; m < NW; ++m) {
+    const int e = tid + m * NT;
+    if (!wok[m]) wv[m][0] = wv[m][1] = wv[m][2] = 0.0;
+    if (e < TX + 1) {
+      wxh[e] = wv[m][0], wxi[e] = wv[m][1], wxd[e] = wv[m][2];
+    } else if (e < (TX + 1) + (TY + 1)) {
+      const int q = e - (TX + 1);
+      wyh[q] = wv[m][0], wyi[q] = wv[m][1], wyd[q] = wv[m][2];
+    } else if (e < NWE) {
+      const int q = e - (TX + 1) - (TY + 1);
+      wzh[q] = wv[m][0], wzi[q] = wv[m][1], wzd[q] = wv[m][2];
+    }
+  }
   // 3. staged values into LDS
 #pragma unroll
   for (int l = 0; l < NL; ++l) {
@@ -391,7 +442,6 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
   __syncthreads();
   if (!own) return;
   const int li = tx + 1, lj = ty + 1;
-  const double ohx = g.h[0][i], ohy = g.h[1][j];
 #pragma unroll
   for (int z = 0; z < KZ; ++z) {
     const int kk = k0 + z;
@@ -400,7 +450,7 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
     const double fx = phi[p][0][lj][li], fy = phi[p][1][lj][li], fz = phi[p][2][lj][li];
     const double kpx = ohx * (phi[p - 1][1][lj][li] - fy + fz - phi[p][2][lj - 1][li]);
     const double kpy = ohy * (phi[p][2][lj][li - 1] - fz + fx - phi[p - 1][0][lj][li]);
-    const double kpz = g.h[2][kk] * (phi[p][0][lj - 1][li] - fx + fy - phi[p][1][lj][li - 1]);
+    const double kpz = ohz[z] * (phi[p][0][lj - 1][li] - fx + fy - phi[p][1][lj][li - 1]);
     const long long v = node_of(g, i, j, kk);
     emit(v, 0, kpx, ou[z][0], od[z][0]);
     emit(v, 1, kpy, ou[z][1], od[z][1]);
@@ -423,16 +473,6 @@ __device__ inline double from_lane(double v, int l) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-__device__ double sum_prev(const double* __restrict__ partials, int n, double* lds) {
-  double s = 0.0;
-  for (int i = flat_tid(); i < n; i += flat_threads()) s += partials[i];
-  s = block_sum(s, lds);
-  __shared__ double bc;
-  if (flat_tid() == 0) bc = s;
-  __syncthreads();
-  return bc;
-}
-
 // ---------------------------------------------------------------------------
 // Seed CG on A0 = A + s0, iteration k (local = k mod B):
 //   stencil: rr_k = sum of the update's partials, beta_{k-1} = rr_k / rr_{k-1};
@@ -451,21 +491,34 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(4))
                                                           const double* __restrict__ dinv, double s0,
                                                           const double* __restrict__ upd_partials,
                                                           double* __restrict__ partials, SolveState* st, int local) {
-  __shared__ double red[16];
+  constexpr int NT = TX * TY;
+  constexpr int NPART = (UPD_BLOCKS + NT - 1) / NT;
+  __shared__ double red[(NT + kWave - 1) / kWave];
   const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const int tid = threadIdx.x + TX * threadIdx.y;
+  // requested before the stencil's own loads so that their round trips
+  // overlap those loads: the update's partials, rr_{k-1} and the block length
+  // (unconditional loads of clamped indices: a load under a branch would be
+  // waited for inside it)
+  double part[NPART];
+#pragma unroll
+  for (int m = 0; m < NPART; ++m) part[m] = upd_partials[min(tid + m * NT, UPD_BLOCKS - 1)];
+  const double rr_prev = st->rrk[(local + 1) & 1];
+  const int B = st->B;
   double beta = 0.0;
   // rr_k from the update's partials, beta_{k-1} = rr_k / rr_{k-1} (rr_{-1} = inf gives 0)
   auto pre = [&]() {
-    const double rr = sum_prev(upd_partials, UPD_BLOCKS, red);
-    const double rr_prev = st->rrk[(local + 1) & 1];
+    double sp = tid < UPD_BLOCKS ? part[0] : 0.0;
+#pragma unroll
+    for (int m = 1; m < NPART; ++m) sp += tid + m * NT < UPD_BLOCKS ? part[m] : 0.0;
+    const double rr = block_total_n<NT>(sp, red, tid);
     beta = rr / rr_prev;
-    if (bid == 0 && flat_tid() == 0) {
+    if (bid == 0 && tid == 0) {
       if (isinf(rr_prev)) {  // first iteration: rr_0 = (g, g) scales the stopping tolerance
         st->rr0 = rr;
         st->tol2 *= rr;
       }
       st->rrk[local & 1] = rr;
-      const int B = st->B;
       const int prev = (local + B - 1) % B;  // the step k-1
       st->beta_h[prev] = beta;
       st->rr_h[prev] = rr;
@@ -493,8 +546,8 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(4))
     auto load = [&](long long v, int c) { return r[c * g.nn + v] + beta * pold[c * g.nn + v]; };
     stencil_tile<double, TX, TY, KZ>(g, dinv, blockIdx.z, load, emit);
   }
-  const double s = block_sum(dot, red);
-  if (flat_tid() == 0) partials[bid] = s;
+  const double s = block_sum_n<NT>(dot, red, tid);
+  if (tid == 0) partials[bid] = s;
 }
 
 __global__ void __launch_bounds__(UPD_T) k_seed_update(long long n, const double* __restrict__ r,
@@ -502,10 +555,17 @@ __global__ void __launch_bounds__(UPD_T) k_seed_update(long long n, const double
                                                        const double* __restrict__ st_partials, int n_st,
                                                        double* __restrict__ partials, SolveState* st, int local) {
   __shared__ double red[UPD_T / 64];
+  const int tid = threadIdx.x;
+  // requested first, so that their round trips overlap the loads of r and q
+  // below: this thread's first stencil partial (clamped index, no branch),
+  // rr_k and B
+  const double part0 = st_partials[min(tid, n_st - 1)];
+  const double rr = st->rrk[local & 1];
+  const int B = st->B;
   // the first UPD_PF grid-stride elements are loaded before the reduction so
   // that their latency overlaps the sum of the stencil's partials
   const long long stride = (long long)gridDim.x * UPD_T;
-  const long long e0 = blockIdx.x * (long long)UPD_T + threadIdx.x;
+  const long long e0 = blockIdx.x * (long long)UPD_T + tid;
   double rv[UPD_PF], qv[UPD_PF];
 #pragma unroll
   for (int m = 0; m < UPD_PF; ++m) {
@@ -513,12 +573,13 @@ __global__ void __launch_bounds__(UPD_T) k_seed_update(long long n, const double
     rv[m] = e < n ? r[e] : 0.0;
     qv[m] = e < n ? q[e] : 0.0;
   }
-  const double pap = sum_prev(st_partials, n_st, red);
-  const double rr = st->rrk[local & 1];
+  // fixed-order sum: this thread's partials in index order, then the block
+  double sp = tid < n_st ? part0 : 0.0;
+  for (int i = tid + UPD_T; i < n_st; i += UPD_T) sp += st_partials[i];
+  const double pap = block_total_n<UPD_T>(sp, red, tid);
   const double alpha = (pap > 0.0 && isfinite(pap)) ? rr / pap : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == 0 && tid == 0) {
     if (!(pap > 0.0 && isfinite(pap))) st->breakdown = 1;
-    const int B = st->B;
     if (local == 0) {  // alpha, beta of the step before this block, for the shift recurrences
       st->carry_alpha = st->alpha_h[B - 1];
       st->carry_beta = st->beta_h[B - 1];
@@ -541,8 +602,8 @@ __global__ void __launch_bounds__(UPD_T) k_seed_update(long long n, const double
     rnext[e] = v;
     acc += v * v;
   }
-  const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  const double s = block_sum_n<UPD_T>(acc, red, tid);
+  if (tid == 0) partials[blockIdx.x] = s;
 }
 
 // Per-shift recurrences for one block of B seed steps, replayed from the
@@ -555,20 +616,27 @@ __global__ void __launch_bounds__(UPD_T) k_seed_update(long long n, const double
 // accumulated as coefficients of the block's starting p and residuals r_l.
 __global__ void __launch_bounds__(64) k_shift_block(const double* __restrict__ upd_partials, SolveState* st) {
   const int j = blockIdx.x, lane = threadIdx.x;
+  constexpr int NPART = (UPD_BLOCKS + kWave - 1) / kWave;
+  __shared__ double red[1];
+  // the update's partials and the state's scalars are all requested before
+  // any is used (one round trip instead of several in sequence)
+  double part[NPART];
+#pragma unroll
+  for (int m = 0; m < NPART; ++m) part[m] = upd_partials[min(lane + m * kWave, UPD_BLOCKS - 1)];
   const int B = st->B;
-  __shared__ int s_active;
-  __shared__ double red[2];
+  const int is_active = st->active[j];
   // the block's last step: (r_{k+1}, r_{k+1}) from the update's partials, beta_k
-  const double rr_last = sum_prev(upd_partials, UPD_BLOCKS, red);
+  double sp = part[0];
+#pragma unroll
+  for (int m = 1; m < NPART; ++m) sp += lane + m * kWave < UPD_BLOCKS ? part[m] : 0.0;
+  const double rr_last = block_total_n<kWave>(sp, red, lane);
   const double beta_last = rr_last / st->rrk[(B - 1) & 1];
-  if (lane == 0) s_active = st->active[j];
   if (j == 0 && lane == 0) {
     st->beta_h[B - 1] = beta_last;
     st->rr_h[B - 1] = rr_last;
     st->k += B;
   }
-  __syncthreads();
-  if (!s_active) {
+  if (!is_active) {
     if (lane == 0) st->apply[j] = 0;
     return;
   }
