@@ -575,6 +575,9 @@ int tem_setup_grid(tem_ctx** out, int nx, int ny, int nz, const double* hx, cons
   g.py = ny + 1;
   g.pz = nz + 1;
   g.nn = (long long)g.px * g.py * g.pz;
+  int n_cu = 0;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) n_cu = 0;
+  g.seed_tile = tem::choose_seed_tile(g, n_cu);
   c->n3 = 3 * g.nn;
   c->nstore = tem::storage_edges(g);
   if (tem::seed_stencil_blocks(g) > tem::kReduceSlots) return fail(nullptr, TEM_EINVAL, "grid too large for this build");

@@ -31,6 +31,7 @@ struct GridArgs {
   const double* h[3];       // widths, length n_a + 1 (last entry 0)
   const double* ih[3];      // 1 / width, last entry 0
   const double* dw[3];      // dual width / mu0 per node, length n_a + 1
+  int seed_tile = -1;       // seed stencil tile shape (index into the launcher table; host side)
 };
 
 // Seed-recurrence scalars and per-shift state; lives in device memory.  The
@@ -143,6 +144,8 @@ void launch_gather_storage(const GridArgs& g, const double2* xpad, const double*
 long long storage_edges(const GridArgs& g);
 int cstencil_partials(const GridArgs& g);
 int seed_stencil_blocks(const GridArgs& g);
+// seed stencil tile shape for a grid on a device with n_cu compute units
+int choose_seed_tile(const GridArgs& g, int n_cu);
 // adjoint: batched COCG (state is an opaque device struct of cocg_state_bytes())
 size_t cocg_state_bytes();
 int cocg_partials(const GridArgs& g, int J);

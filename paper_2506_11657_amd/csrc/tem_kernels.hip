@@ -485,7 +485,7 @@ __device__ inline double from_lane(double v, int l) {
 // 4 waves per SIMD keeps two 512-thread tiles resident per CU (the LDS of
 // two tiles fits); the staged registers must then fit in 128 VGPRs
 template <int TX, int TY, int KZ, bool B3D>
-__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(4))) k_seed_stencil(GridArgs g, const double* __restrict__ r,
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(TX * TY * KZ > 512 ? 2 : 4))) k_seed_stencil(GridArgs g, const double* __restrict__ r,
                                                           const double* __restrict__ pold,
                                                           double* __restrict__ pnew, double* __restrict__ q,
                                                           const double* __restrict__ dinv, double s0,
@@ -1359,17 +1359,34 @@ struct TileShape {
 static const TileShape kSeedTiles[] = {{32, 4, 2}, {32, 4, 4}, {64, 2, 2}, {64, 2, 4}, {64, 4, 4},
                                        {64, 4, 8}, {32, 8, 4}, {32, 2, 2}, {64, 1, 4}, {64, 2, 8},
                                        {32, 4, 2}, {32, 4, 4}, {64, 2, 2}, {64, 4, 2}, {32, 8, 2}, {64, 2, 4},
-                                       {64, 4, 1}, {64, 8, 1}, {32, 8, 1}, {64, 2, 1}};
+                                       {64, 4, 1}, {64, 8, 1}, {32, 8, 1}, {64, 2, 1}, {64, 8, 2}};
+constexpr int kNumSeedTiles = (int)(sizeof(kSeedTiles) / sizeof(kSeedTiles[0]));
 static int pick_seed_tile(const GridArgs& g) {
-  // fixed per process (thread-safe static initialization); TEM_SEED_TILE overrides
+  // TEM_SEED_TILE overrides the per-grid choice (read once per process)
   static const int v = [] {
     const char* env = getenv("TEM_SEED_TILE");
-    int t = env ? atoi(env) : 17;
-    if (t < 0 || t >= (int)(sizeof(kSeedTiles) / sizeof(kSeedTiles[0]))) t = 17;
-    return t;
+    const int t = env ? atoi(env) : -1;
+    return t >= 0 && t < kNumSeedTiles ? t : -1;
   }();
-  (void)g;
-  return v;
+  if (v >= 0) return v;
+  return g.seed_tile >= 0 && g.seed_tile < kNumSeedTiles ? g.seed_tile : 17;
+}
+
+static long long seed_tiles_of(const GridArgs& g, const TileShape& t) {
+  return (long long)((g.nx + t.tx - 1) / t.tx) * ((g.ny + t.ty - 1) / t.ty) * ((g.nz + t.kz - 1) / t.kz);
+}
+
+// (64, 8, 1) tiles, two resident per CU, unless they fill every CU at least
+// twice while (64, 8, 2) tiles (one per CU, 107 KB of LDS) fit in a single
+// round: then the two-plane tile re-reads a third fewer halo values per node
+// and was measured 3.7% faster per launch (64^3); with several rounds the
+// one-plane tile is faster (128^3).
+int choose_seed_tile(const GridArgs& g, int n_cu) {
+  constexpr int kOnePlane = 17, kTwoPlane = 20;
+  if (n_cu > 0 && seed_tiles_of(g, kSeedTiles[kOnePlane]) >= 2LL * n_cu &&
+      seed_tiles_of(g, kSeedTiles[kTwoPlane]) <= n_cu)
+    return kTwoPlane;
+  return kOnePlane;
 }
 
 static dim3 seed_stencil_grid(const GridArgs& g) {
@@ -1444,6 +1461,7 @@ void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold,
     TEM_SEED_CASE(17, 64, 8, 1)
     TEM_SEED_CASE(18, 32, 8, 1)
     TEM_SEED_CASE(19, 64, 2, 1)
+    TEM_SEED_CASE(20, 64, 8, 2)
   }
 #undef TEM_SEED_CASE
 }
