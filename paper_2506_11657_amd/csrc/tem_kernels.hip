@@ -1362,13 +1362,6 @@ static const TileShape kSeedTiles[] = {{32, 4, 2}, {32, 4, 4}, {64, 2, 2}, {64, 
                                        {64, 4, 1}, {64, 8, 1}, {32, 8, 1}, {64, 2, 1}, {64, 8, 2}};
 constexpr int kNumSeedTiles = (int)(sizeof(kSeedTiles) / sizeof(kSeedTiles[0]));
 static int pick_seed_tile(const GridArgs& g) {
-  // TEM_SEED_TILE overrides the per-grid choice (read once per process)
-  static const int v = [] {
-    const char* env = getenv("TEM_SEED_TILE");
-    const int t = env ? atoi(env) : -1;
-    return t >= 0 && t < kNumSeedTiles ? t : -1;
-  }();
-  if (v >= 0) return v;
   return g.seed_tile >= 0 && g.seed_tile < kNumSeedTiles ? g.seed_tile : 17;
 }
 
@@ -1383,6 +1376,12 @@ static long long seed_tiles_of(const GridArgs& g, const TileShape& t) {
 // one-plane tile is faster (128^3).
 int choose_seed_tile(const GridArgs& g, int n_cu) {
   constexpr int kOnePlane = 17, kTwoPlane = 20;
+  // TEM_SEED_TILE (an index into the table) overrides the choice for
+  // contexts created while it is set
+  if (const char* env = getenv("TEM_SEED_TILE")) {
+    const int t = atoi(env);
+    if (t >= 0 && t < kNumSeedTiles) return t;
+  }
   if (n_cu > 0 && seed_tiles_of(g, kSeedTiles[kOnePlane]) >= 2LL * n_cu &&
       seed_tiles_of(g, kSeedTiles[kTwoPlane]) <= n_cu)
     return kTwoPlane;

@@ -120,6 +120,27 @@ def test_forward_parity_ragged_tiles_two_sources(tem):
         assert np.all(ed <= 1e-8 * dn + 1e-9 * Sd)
 
 
+@pytest.mark.parametrize("tile", ["17", "20"])
+def test_stencil_tiles_parity_ragged(tem, tile, monkeypatch):
+    """Both stencil tiles the library chooses between, the one-plane (64, 8, 1)
+    and the two-plane (64, 8, 2), on a grid with ragged tails in x, y and an
+    odd nz (a two-plane tile holds one plane): every shift matches the direct
+    solve (TEM_SEED_TILE fixes the tile for contexts created while it is set)."""
+    monkeypatch.setenv("TEM_SEED_TILE", tile)
+    rng = np.random.default_rng(21)
+    hx, hy, hz = rng.uniform(8, 25, 70), rng.uniform(8, 25, 11), rng.uniform(8, 25, 9)
+    sigma = np.full((9, 11, 70), 1e-5)
+    sigma[:5] = 10 ** rng.uniform(-2.5, -0.5, (5, 11, 70))
+    wl = W.Workload("ragged2", hx, hy, hz, 5, sigma, loops=[W.Loop(10, 40, 2, 8, 1.0)],
+                    receivers=[(25, 5), (60, 3)], t=W.log_channels(1e-5, 1e-3, 10))
+    ctx, stats, res = _parity(tem, wl, 16, method="banded")
+    ex, eu, un, Sk, ed, dn, Sd = res[0]
+    print("tile %s: iterations %d, max shift err %.2e" % (tile, stats["iterations"], ex.max()))
+    assert stats["converged"] and ex.max() <= 1e-9
+    assert np.all(eu <= 1e-8 * un + 1e-9 * Sk)
+    assert np.all(ed <= 1e-8 * dn + 1e-9 * Sd)
+
+
 def test_fields_mfma_contraction_matches(tem):
     """Full fields U (storage order, MFMA FP64 contraction) equal Re(X C) of the
     returned solutions to rounding, and the receivers agree with Q U."""
