@@ -835,6 +835,11 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
                               kRefinePassTol, cap, cs, its, caps.data());
           if (r2 != TEM_OK && r2 != TEM_ENOCONV) return r2;
           for (int j = 0; j < J; ++j) S.unknown_updates += (double)ctx->nunk * cs.iters[j];
+          // a later pass of shift j may take up to 16x the iterations of this
+          // one (at least 2048): an FP32 correction that stagnates on a stiff
+          // grid would otherwise run to twice the sweep's length every pass
+          for (int j = 0; j < J; ++j)
+            if ((todo >> j) & 1ull) caps[j] = std::min(caps[j], std::max(2048, 16 * cs.iters[j]));
           // d_j in FP64, w_j = (A + s_j) d_j, dots against rho_j (the P buffer)
           double2* D = (double2*)ctx->refine64.p;
           double2* Wv = D + vn;
