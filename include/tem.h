@@ -95,8 +95,9 @@ typedef struct {
   int refine_max;    /* precision 1: cap on refinement passes; <= 0 selects 8; a shift
                         still above rtol after the cap gives TEM_ENOCONV */
   int keep_solutions;/* nonzero: keep X on the device for tem_adjoint / tem_solutions */
-  int profile;       /* nonzero: time every solver kernel launch with HIP events on the
-                        context stream (fills kernel_ms / kernel_launches of tem_stats) */
+  int profile;       /* nonzero: one solver block in 16 is issued as direct launches whose
+                        dispatches record HIP events (fills kernel_ms / kernel_launches of
+                        tem_stats with the sampled launches); results are unchanged */
 } tem_solve_opts;
 
 /* kernel classes reported by tem_stats.kernel_ms */
