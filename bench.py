@@ -204,8 +204,8 @@ def main():
                     help="also serve the same trace one request at a time (no overlap)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(sharding over poles or requests is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(it would shard the poles or the requests across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import torch

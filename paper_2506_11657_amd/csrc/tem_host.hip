@@ -580,7 +580,7 @@ int tem_setup_grid(tem_ctx** out, int nx, int ny, int nz, const double* hx, cons
   g.seed_tile = tem::choose_seed_tile(g, n_cu);
   c->n3 = 3 * g.nn;
   c->nstore = tem::storage_edges(g);
-  if (tem::seed_stencil_blocks(g) > tem::kReduceSlots) return fail(nullptr, TEM_EINVAL, "grid too large for this build");
+  if (tem::seed_stencil_blocks(g) > tem::kReduceSlots) return fail(nullptr, TEM_EINVAL, "grid too large: more stencil tiles than partial-sum slots");
   c->nunk = (long long)nx * (ny - 1) * (nz - 1) + (long long)(nx - 1) * ny * (nz - 1) + (long long)(nx - 1) * (ny - 1) * nz;
   // axis arrays: h, 1/h, dual/mu0 per axis, each padded to n+1
   const int L = std::max(nx, std::max(ny, nz)) + 1;
