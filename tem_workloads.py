@@ -223,9 +223,11 @@ def serving_trace(seed: int = 7, n_req: int = 400, rate: float = 200.0) -> list:
 
 
 def serving_request(n: int, n_src: int, seed: int) -> Workload:
-    """One serving request: graded grid of n cells per axis keeping the extent
-    of the 64^3 grid (growth 1.1**(64/n)), blocky conductivity, n_src loops of
-    100 m at distinct seeded surface positions in the core."""
+    """One serving request: graded grid of n cells per axis, a 12-cell 10 m
+    core and growth 1.1**(64/n) outwards (horizontal extent 0.78 km at n = 32,
+    1.6 km at 48, 2.5 km at 64 as the 64^3 benchmark grid, 4.5 km at 96),
+    blocky conductivity, n_src loops of 100 m at distinct seeded surface
+    positions in the core."""
     rng = np.random.default_rng(seed)
     g = 1.1 ** (64.0 / n)
     core = 12
