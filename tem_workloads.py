@@ -250,3 +250,45 @@ def serving_request(n: int, n_src: int, seed: int) -> Workload:
         loops.append(Loop(i0, i0 + 10, j0, j0 + 10, 1.0))
     return Workload("serve%d" % n, hx, hx.copy(), hz, n_earth, sigma, loops=loops,
                     receivers=[(n // 2, n // 2)], t=log_channels(1e-6, 1e-2, 40), degree=44)
+
+
+# ---------------------------------------------------------------------------
+# Ragged multi-tile test grids (random widths, several stencil tiles with
+# partial tails in x, y and z); shared by the oracle's floor measurement and
+# the GPU parity tests
+# ---------------------------------------------------------------------------
+
+def ragged37(sigma_air: float = SIGMA_AIR) -> Workload:
+    """37 x 10 x 9 cells of 8-25 m, random earth in the bottom 5 layers, two
+    loops (1 A and 2.5 A), three receivers, 12 channels in [1e-5, 1e-3] s."""
+    rng = np.random.default_rng(3)
+    hx, hy, hz = rng.uniform(8, 25, 37), rng.uniform(8, 25, 10), rng.uniform(8, 25, 9)
+    sigma = np.full((9, 10, 37), sigma_air)
+    sigma[:5] = 10 ** rng.uniform(-2.5, -0.5, (5, 10, 37))
+    return Workload("ragged37", hx, hy, hz, 5, sigma,
+                    loops=[Loop(3, 12, 2, 7, 1.0), Loop(20, 33, 3, 8, 2.5)],
+                    receivers=[(7, 4), (25, 5), (30, 1)], t=log_channels(1e-5, 1e-3, 12), degree=16)
+
+
+def ragged70(sigma_air: float = 1e-5) -> Workload:
+    """70 x 11 x 9 cells of 8-25 m (odd nz: a two-plane stencil tile holds one
+    plane at the top), random earth in the bottom 5 layers, one loop, two
+    receivers, 10 channels in [1e-5, 1e-3] s."""
+    rng = np.random.default_rng(21)
+    hx, hy, hz = rng.uniform(8, 25, 70), rng.uniform(8, 25, 11), rng.uniform(8, 25, 9)
+    sigma = np.full((9, 11, 70), sigma_air)
+    sigma[:5] = 10 ** rng.uniform(-2.5, -0.5, (5, 11, 70))
+    return Workload("ragged70", hx, hy, hz, 5, sigma, loops=[Loop(10, 40, 2, 8, 1.0)],
+                    receivers=[(25, 5), (60, 3)], t=log_channels(1e-5, 1e-3, 10), degree=16)
+
+
+def ragged29(sigma_air: float = SIGMA_AIR) -> Workload:
+    """29 x 13 x 10 cells of 8-25 m, random earth in the bottom 6 layers, two
+    loops (1 A and -2 A), two receivers, 12 channels in [1e-5, 1e-3] s."""
+    rng = np.random.default_rng(11)
+    hx, hy, hz = rng.uniform(8, 25, 29), rng.uniform(8, 25, 13), rng.uniform(8, 25, 10)
+    sigma = np.full((10, 13, 29), sigma_air)
+    sigma[:6] = 10 ** rng.uniform(-2.5, -0.5, (6, 13, 29))
+    return Workload("ragged29", hx, hy, hz, 6, sigma,
+                    loops=[Loop(3, 12, 2, 9, 1.0), Loop(15, 26, 4, 10, -2.0)],
+                    receivers=[(7, 5), (20, 6)], t=log_channels(1e-5, 1e-3, 12), degree=16)

@@ -2,6 +2,9 @@
 Sec. 3.3 against brute-force dense exp(-t M^-1 K) b, exact eigenvector
 behaviour, discrete charge conservation, two independent direct solvers,
 monotone decay, finite differences and the adjoint identity."""
+import json
+import os
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -179,3 +182,42 @@ def test_adjoint_bilinear_identity():
         dX[:, j] = -D.solve_shifted(P, [sj], sj * dM * X[:, j])[:, 0]
     Jdm = (P.Q @ D.contract(dX, C)).T
     assert np.isclose(np.sum(w * Jdm), g @ dm, rtol=1e-10)
+
+
+FLOORS = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_floors.json")))["grids"]
+
+
+@pytest.mark.parametrize("name", ["plain16", "ragged37"])
+def test_parity_floor_two_direct_solvers(name):
+    """Where the oracle itself stops being exact (the cancellation floor of
+    the residue sum, Sec. 3.2 product S R in the Sec. 3.3 M-norm): the two
+    independent direct solvers (banded LU after RCM, SuperLU) agree per
+    channel to eta_or S_k with eta_or <= 1e-10, S_k = sum_j |c_jk| ||x_j||_M
+    (measured: 3.5e-11 on plain16, 4.1e-12 on ragged37).  So a GPU channel bar
+    of the form eps ||u_k|| + eta S_k with eta >= 1e-10 is not tighter than
+    the reference can resolve.  Channels where the two solvers differ by more
+    than 1e-9 ||u_k|| (8..20 of plain16, 10..12 of ragged37) cannot pin a 1e-8
+    relative claim: for them the GPU parity tests check only the per-shift
+    bound, and they are reported as parity unpinned at 1e-8 relative.  The
+    measurement is recomputed here and compared with the stored one
+    (tests/golden/oracle_floors.json, written by make_oracle_floors.py)."""
+    wl, m = {"plain16": (W.cfg_plain16(), 38), "ragged37": (W.ragged37(), 16)}[name]
+    fit = rkfit.rkfit(wl.t, m)
+    s, C = rkfit.shifts_and_coefficients(fit)
+    P = yee.Problem(wl)
+    for src, ref in enumerate(FLOORS[name]):
+        Xb = D.solve_shifted(P, s, P.F[:, src], "banded")
+        Xs = D.solve_shifted(P, s, P.F[:, src], "splu")
+        xn = D.m_norm(P, Xs)
+        Sk = np.abs(C).T @ xn
+        Us = D.contract(Xs, C)
+        un = D.m_norm(P, Us)
+        eu = D.m_norm(P, D.contract(Xb, C) - Us)
+        print("%s source %d: oracle floor max eu/S_k %.2e; 1e-8-relative channels %s; unpinned %s"
+              % (name, src, (eu / Sk).max(), np.where(eu <= 1e-9 * un)[0] + 1, np.where(eu > 1e-9 * un)[0] + 1))
+        assert (eu / Sk).max() <= 1e-10
+        # the stored measurement is reproduced (rounding-level changes only)
+        assert (eu / Sk).max() <= 10 * max(ref["eu_over_Sk"])
+        assert np.sum(eu <= 1e-9 * un) >= sum(v <= 1e-9 for v in ref["eu_over_un"]) - 1
+        # the early, resolved channels are pinned outright
+        assert np.all(eu[:5] <= 1e-9 * un[:5])
