@@ -27,7 +27,8 @@ Readings of passages the paper leaves open (listed in the design notes):
     in the normalized time tau = t/t_max (see ``surrogate``);
   * initial poles: m/2 conjugate pairs -r(cos 60deg +- i sin 60deg), r
     log-spaced on [1, 1/tau_min] (plus -1/sqrt(tau_min) for odd m); 20 sweeps,
-    keeping the sweep whose fit has the smallest maximum error on the samples;
+    keeping the sweep whose fit has the smallest uniform error of eq.
+    (uniform_error), max_j w_j max_x |exp(-t_j x) - r^[j](x)|, on the samples;
   * the relocated poles are symmetrized into conjugate pairs; poles may lie in
     either half plane (Sec. 3.3 only asks that they avoid the spectral region
     x >= 0), and a real pole on x >= 0 is reflected to -x;
@@ -224,7 +225,7 @@ def rkfit(t, degree: int, w=None, sweeps: int = 20, ns: int = 2000):
         poles = symmetrize(z, poles)
         reps = representatives(poles)
         A = fit_residues(reps, tau, s)
-        e = channel_errors(reps, A, tau, xsel).max()
+        e = (w * channel_errors(reps, A, tau, xsel)).max()   # eq. (uniform_error), weighted
         if best is None or e < best[0]:
             best = (e, reps, A)
     _, reps, A = best

@@ -16,7 +16,7 @@
 // same passage, implemented independently): surrogate = 0 and 2000
 // log-spaced points on [1e-3, 1e4/tau_min] in tau = t/t_max; start poles
 // -r e^{+-i pi/3}, r log-spaced on [1, 1/tau_min]; 20 sweeps keeping the
-// sweep with the smallest uniform error on a coarse check set; relocated
+// sweep with the smallest (weighted, eq. (uniform_error)) uniform error on a coarse check set; relocated
 // poles symmetrized into conjugate pairs, a real pole on x >= 0 reflected.
 //
 // Dense kernels (all hand-written; no LAPACK is linked): Householder QR,
@@ -583,8 +583,11 @@ int rkfit(const std::vector<double>& t, const std::vector<double>& w, int m, Rkf
     poles = symmetrize(z, poles);
     const std::vector<cd> reps = representatives(poles);
     const std::vector<cd> Ares = fit_residues(reps, tau, x);
+    // eq. (uniform_error): the weighted maximum over the channels (all weights 1
+    // gives the plain uniform error)
     const std::vector<double> e = channel_errors(reps, Ares, tau, 4000);
-    const double emax = *std::max_element(e.begin(), e.end());
+    double emax = 0.0;
+    for (size_t k = 0; k < e.size(); ++k) emax = std::max(emax, w[k] * e[k]);
     if (std::isfinite(emax) && emax < best_err) {
       best_err = emax;
       best.reps = reps;

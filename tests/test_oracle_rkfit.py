@@ -61,11 +61,17 @@ def test_table1_degree_reaches_tolerance(ratio, tol, m):
     assert fit["err"].max() <= 1.2 * tol
 
 
-def test_fig1_poles_pairs_and_closest_pair():
+def test_fig1_poles_pairs_and_printed_pair():
     """Fig. 1 (bottom): degree 28 on [1e-3, 1] with 31 channels gives 14
-    conjugate pairs away from x >= 0, one of them within 10 % of the printed
-    -7.574 +- 12.45i (5 % off with our reading of the unstated surrogate,
-    which also puts two pairs nearer the origin)."""
+    conjugate pairs away from x >= 0, and the printed pair -7.574 +- 12.45i is
+    among them (within 10 %).  The caption calls it the pair closest to the
+    origin; this reading of the unstated surrogate and start poles does not
+    reproduce that: its closest pair lies near the negative real axis
+    (|Im| < 3, |xi| about 10).  Thirty variants (surrogate range and sample
+    count, start poles on a 60 degree ray or at infinity, 10 or 20 sweeps,
+    best or last sweep, reflection into Re xi < 0) all gave such a near-real
+    closest pair, so the difference is kept as a stated deviation and pinned
+    here as measured."""
     c = COUNTS
     t = np.logspace(np.log10(c["fig1_window"][0]), np.log10(c["fig1_window"][1]), c["fig1_channels"])
     fit = R.rkfit(t, c["fig1_degree"])
@@ -73,6 +79,8 @@ def test_fig1_poles_pairs_and_closest_pair():
     assert fit["pairs"].sum() == c["fig1_pair_count"] and len(xi) == c["fig1_pair_count"]
     target = complex(*c["fig1_closest_pair"])
     assert np.min(np.abs(xi - target)) / abs(target) < 0.10
+    closest = xi[np.argmin(np.abs(xi))]
+    assert abs(closest) < abs(target) and abs(closest.imag) < 3.0
     # distance from the spectral region [0, inf)
     dist = np.where(xi.real >= 0, np.abs(xi.imag), np.abs(xi))
     assert np.all(dist > 1.0)
@@ -127,3 +135,27 @@ def test_conjugate_symmetry_of_full_family():
         if pair:
             full += a.conj()[None, :] / (x[:, None] - np.conj(p))
     assert np.abs(full.imag).max() <= 1e-12 * np.abs(full.real).max()
+
+
+def test_weighted_rkfit_moves_accuracy_to_late_channels():
+    """Sec. 5.2: weights w_j ~ t_j^{5/2} in eq. (rkfit) offset the t^{-5/2}
+    late-time decay of dB_z/dt.  At degree 38 on [1e-5, 1e-2] (20 channels),
+    the weighted fit lowers the error of eq. (error) at the last channel by
+    more than 100x and raises it at the first (measured: 9.4e-10 -> 4.2e-12 and
+    1.3e-9 -> 1.1e-7), it beats the unweighted fit on the weighted uniform error
+    of eq. (uniform_error) that it targets, and the relative error bound
+    err_k / t_k^{-5/2} of a transient decaying like t^{-5/2} is flatter (its
+    worst channel is lower).  The host fit (tem_poles with w) agrees with the
+    oracle's to a factor of 5 on every channel."""
+    from paper_2506_11657_amd import tem as T
+    t = np.logspace(-5, -2, 20)
+    w = (t / t.max()) ** 2.5
+    plain = R.rkfit(t, 38)
+    weighted = R.rkfit(t, 38, w=w)
+    e0, e1 = plain["err"], weighted["err"]
+    assert e1[-1] <= 1e-2 * e0[-1] and e1[0] >= e0[0]
+    assert (w * e1).max() <= (w * e0).max()
+    decay = (t / t[0]) ** -2.5
+    assert (e1 / decay).max() < (e0 / decay).max()
+    _, _, eh = T.poles(t, 38, w=w)
+    assert np.all(eh <= 5 * e1) and np.all(e1 <= 5 * eh)
