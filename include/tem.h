@@ -74,19 +74,21 @@ typedef struct { int i, j; } tem_receiver;
 
 typedef struct {
   int precision;     /* 0: FP64 Krylov sweeps.  1: the multi-shift sweep keeps the complex
-                        per-shift vectors x_j, p_j in FP32 (the shared real seed recurrence
-                        stays FP64) and stops at a scaled residual of 1e-6; FP64 residuals
-                        rho_j then drive refinement passes, each a batched COCG with complex
-                        FP32 vectors on (K + s_j M) d_j = rho_j to a 1e-2 reduction and
-                        x_j += omega_j d_j in FP64 with the step omega_j minimizing the FP64
-                        residual, so no pass raises it.  On stiff grids (seed solves of 1e4+
-                        iterations) FP32 Krylov corrections stagnate and the call returns
-                        TEM_ENOCONV with the best iterate.
-                        Contraction and receivers are FP64 in both. */
+                        per-shift search directions p_j in FP32 (the iterates x_j, the shared
+                        real seed recurrence and its residuals stay FP64) and stops at a
+                        recursive scaled residual of 1e-10; FP64 residuals rho_j then drive
+                        refinement passes, each a batched COCG with complex FP32 vectors on
+                        (K + s_j M) d_j = rho_j to a 1e-2 reduction and x_j += omega_j d_j in
+                        FP64 with the step omega_j minimizing the FP64 residual, so no pass
+                        raises it.  Every pass is bounded (8192 COCG iterations per shift, and
+                        a shift whose correction stops improving by 10% over 1024 iterations
+                        stops early); a shift whose FP64 residual falls by less than 10% in a
+                        pass is not refined further.  Contraction and receivers are FP64. */
   double rtol;       /* per-shift target in the scaled system y = M^1/2 x, g = M^-1/2 f:
                         precision 0 stops shift j when |zeta_j| ||r||_2 <= rtol ||g||_2
                         (<= 0 selects 1e-12); precision 1 refines until the FP64 residual
-                        ||g - (A + s_j) y_j||_2 <= rtol ||g||_2 (<= 0 selects 3e-8) */
+                        ||g - (A + s_j) y_j||_2 <= rtol ||g||_2 (<= 0 selects 1e-5; with
+                        1e-8 S/m air FP32 corrections stop improving near 1e-6) */
   int max_iter;      /* cap on seed iterations per solve; <= 0 selects 2000000 */
   int block;         /* iterations between deferred shift updates (8, 16, 32 or 64; other
                         values round down); <= 0 selects 64 */
@@ -98,6 +100,16 @@ typedef struct {
   int profile;       /* nonzero: one solver block in 16 is issued as direct launches whose
                         dispatches record HIP events (fills kernel_ms / kernel_launches of
                         tem_stats with the sampled launches); results are unchanged */
+  int method;        /* 0: the shifted iterates x_j and directions p_j are kept on the device
+                        (J complex vectors each) and updated every block.  1: two-pass form
+                        with no per-shift vectors: pass 1 runs the shared seed recurrence
+                        alone, recording its coefficients and the receiver values of its
+                        residuals, and the data follow from the shifted recurrences replayed
+                        on the host (one pass when no fields are requested); with fields,
+                        pass 2 regenerates the residuals bitwise and accumulates every
+                        channel as (entries x 64) x (64 x T) FP64 MFMA products.  Method 1 is
+                        FP64 only, keeps no solutions (keep_solutions must be 0) and reports
+                        no true residuals (-1). */
 } tem_solve_opts;
 
 /* kernel classes reported by tem_stats.kernel_ms */
@@ -122,7 +134,9 @@ typedef struct {
 
 /* Create a context for an nx*ny*nz grid with cell widths hx[nx], hy[ny], hz[nz]
  * [m] (all > 0 and finite) and the ground surface at node plane k_surface
- * (0 < k_surface < nz).  device: HIP device ordinal.  hip_stream: a hipStream_t
+ * (0 < k_surface < nz).  The grid plays the role of the mesh T_h of Sec. 2.2
+ * (a tensor grid of hexahedra with edge unknowns instead of the paper's
+ * tetrahedra), inside the PEC box of the Sec. 2.1 boundary condition.  device: HIP device ordinal.  hip_stream: a hipStream_t
  * cast to void*, or NULL for the default stream.  On success *ctx owns device
  * memory for the operator coefficients; no conductivity is set yet. */
 int tem_setup_grid(tem_ctx **ctx, int nx, int ny, int nz,
@@ -175,6 +189,18 @@ int tem_forward(tem_ctx *ctx, const tem_loop *src, int n_src,
  * since the last tem_set_conductivity. */
 int tem_adjoint(tem_ctx *ctx, const double *w, double *grad_log_sigma, tem_stats *stats);
 
+/* Jacobian action (Sec. 4, "Using iterative solvers": the action J x that
+ * CGLS needs beside J^T y, which tem_adjoint gives): for a change dm[c] of
+ * ln sigma per cell ([nz][ny][nx], host), the first-order change of the data
+ * of the last tem_forward,
+ *   ddata[(s*T + k)*n_rx + r] = Re sum_j c_j(t_k) q_r . dx_j   (host),
+ *   (K + s_j M) dx_j = -s_j (dM/d ln sigma . dm) x_j,   s_j = -xi_j,
+ * where dM/d ln sigma_c = sigma_c V_c / 4 on the 12 edges of cell c.  The J
+ * sensitivity systems have different right-hand sides and are solved by one
+ * batched FP64 COCG per source.  Needs the forward's solutions
+ * (keep_solutions), else TEM_ESTATE. */
+int tem_jacobian_apply(tem_ctx *ctx, const double *dm, double *ddata, tem_stats *stats);
+
 /* Copy the stored solutions x_j of source s (storage edge order, complex):
  * X[2*(j*n_storage + e)] (re, im), host.  Needs keep_solutions. */
 int tem_solutions(tem_ctx *ctx, int s, double *X);
@@ -183,6 +209,38 @@ int tem_solutions(tem_ctx *ctx, int s, double *X);
  * storage edge order (host, interleaved); boundary entries of x are ignored
  * and those of y are zero.  For operator checks. */
 int tem_apply(tem_ctx *ctx, double shift_re, double shift_im, const double *x, double *y);
+
+/* Solve engine (serving, form 5): a worker thread on `device` that advances
+ * the multi-shift solves of every context attached to it together, in
+ * batched launches replayed as HIP graphs: per seed iteration one stencil
+ * launch and one update launch cover the tiles of every job (the loop sources
+ * and adjoint receiver rows of all attached contexts' calls in progress), and
+ * per 64 iterations one shift-block and one block-update launch cover all
+ * their poles.  Jobs join and leave at 64-iteration boundaries.  The poles of
+ * all systems are independent work (Sec. 3.2, eq. (rmj); Sec. 5.3 runs them
+ * in parallel processes); here several requests' poles share every launch.
+ * max_jobs: jobs per batch (1..16, <= 0 selects 16); more wait for a place.
+ * Each job's arithmetic (tiles, reductions and their order) does not depend
+ * on the other jobs in its batch, so results are bitwise the same alone or
+ * batched.  FP64 sweeps only: precision-1 calls of attached contexts run
+ * their own launches.  Destroy an engine only after every call of its
+ * attached contexts has returned. */
+typedef struct tem_engine tem_engine;
+int tem_engine_create(tem_engine **eng, int device, int max_jobs);
+
+/* Route the FP64 multi-shift solves of ctx (forward and adjoint) through eng
+ * (NULL detaches).  ctx and eng must be on the same device.  Calls on ctx stay
+ * synchronous for its caller; several threads, each with its own context,
+ * share the engine.  A solve through the engine always uses 64-iteration
+ * blocks (tem_solve_opts.block and .profile are ignored). */
+int tem_attach_engine(tem_ctx *ctx, tem_engine *eng);
+
+/* Batching statistics: blocks launched, job-blocks (sum over blocks of the jobs
+ * in each), the most jobs and the most distinct contexts in one block. */
+int tem_engine_stats(tem_engine *eng, long long *blocks, long long *job_blocks, int *max_jobs,
+                     int *max_contexts);
+
+void tem_engine_destroy(tem_engine *eng);
 
 /* Sizes: n_storage edges and n interior unknowns of the context's grid. */
 int tem_sizes(const tem_ctx *ctx, long long *n_storage, long long *n_unknowns);

@@ -3,11 +3,18 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
+#include <cstddef>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
+#include <functional>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/tem.h"
@@ -26,13 +33,19 @@ thread_local std::string g_global_error;
 // (about n_rx seed sweeps); beyond it one batched COCG over the J shifted
 // systems (about J complex solves) costs less.
 constexpr int kAdjointMultishiftMaxRx = 64;
-// precision 1: the sweep with complex FP32 shift vectors stops at this scaled
-// residual (their storage rounding sits near it); FP64 residual refinement then
-// drives every shift to the requested rtol (default kRefineTarget), each pass
-// reducing the correction system's residual by kRefinePassTol
-constexpr double kSweepTolFP32 = 1e-6;
-constexpr double kRefineTarget = 3e-8;
+// precision 1: the sweep (FP64 iterates y_j, complex FP32 directions p_j) stops
+// at the recursive tolerance kSweepTolFP32, below the M-norm error that the
+// FP32 directions leave (a few 1e-8); FP64 residual refinement then drives
+// every shift to the requested rtol (default kRefineTarget) on its FP64
+// residual, each pass reducing the correction system's residual by
+// kRefinePassTol.  The FP32 rounding noise of the stiff (air) modes dominates
+// that residual: each pass cuts it about 100x, down to a floor near 1e-6 on
+// grids with 1e-8 S/m air, where FP32 corrections stop helping.
+constexpr double kSweepTolFP32 = 1e-10;
+constexpr double kRefineTarget = 1e-5;
 constexpr double kRefinePassTol = 1e-2;
+constexpr int kRefinePassCap = 8192;  // COCG iterations per shift in one refinement pass
+constexpr int kRefineStall = 1024;    // ... and without a 10% residual reduction
 
 struct DevBuf {
   void* p = nullptr;
@@ -47,7 +60,7 @@ constexpr int kMaxConcurrentSolves = 4;
 
 // Workspace of one multi-shift solve.
 struct SolveSlot {
-  DevBuf R, pbuf, q, partials, gvec, P, y32;  // ring, seed p (2), q, partial sums, g, per-shift p_j, FP32 y_j
+  DevBuf R, pbuf, q, partials, gvec, P;  // ring, seed p (2), q, partial sums, g, per-shift p_j
   tem::SolveState* d_state = nullptr;
   void* head = nullptr;          // pinned copies of the solver head, one per block in flight
   hipStream_t stream = nullptr;  // library-owned, default priority
@@ -59,6 +72,7 @@ struct SolveSlot {
 
 struct tem_ctx {
   int device = 0;
+  tem_engine* engine = nullptr;     // solve engine the multi-shift solves are submitted to (or none)
   hipStream_t stream = nullptr;       // caller's stream (may be the null stream)
   hipStream_t work = nullptr;         // library-owned stream: every kernel runs here
   hipEvent_t order_ev = nullptr;      // orders work after the caller's stream
@@ -228,7 +242,7 @@ int ensure_slots(tem_ctx* ctx, int n) {
 }
 
 void release_slot(SolveSlot& sl) {
-  for (DevBuf* b : {&sl.R, &sl.pbuf, &sl.q, &sl.partials, &sl.gvec, &sl.P, &sl.y32}) release(*b);
+  for (DevBuf* b : {&sl.R, &sl.pbuf, &sl.q, &sl.partials, &sl.gvec, &sl.P}) release(*b);
   if (sl.d_state) (void)hipFree(sl.d_state);
   if (sl.head) (void)hipHostFree(sl.head);
   if (sl.ev) (void)hipEventDestroy(sl.ev);
@@ -237,17 +251,344 @@ void release_slot(SolveSlot& sl) {
   if (sl.stream) (void)hipStreamDestroy(sl.stream);
 }
 
+// ---------------------------------------------------------------------------
+// Solve engine: one worker thread per engine advances the multi-shift solves
+// submitted by every attached context (the loop sources and adjoint receiver
+// rows of all admitted requests) together, 64 seed iterations at a time, as a
+// HIP graph of batched launches: per iteration one seed stencil launch and one
+// seed update launch cover every job's tiles, then one shift-block and one
+// block-update launch cover every job's shifts.  Jobs join at block
+// boundaries (their seed initialisation is queued before the next block) and
+// leave when all their shifts have converged; the graph is rebuilt when the
+// set of jobs changes.  Two blocks stay in flight: the worker reads the heads
+// of block b while block b+1 runs.  The poles are independent work (Sec. 5.3
+// parallelizes over them across processes); here the poles of several
+// requests share every launch.
+// ---------------------------------------------------------------------------
+struct EngineJob {
+  tem_ctx* ctx = nullptr;
+  int slot = 0;
+  double2* Y = nullptr;
+  int J = 0;
+  double s0 = 0.0;
+  int max_iter = 0;
+  std::unique_ptr<SolveState> init;    // initial device state (host copy)
+  hipEvent_t ready = nullptr;          // right-hand side and buffers ready (context stream)
+  hipEvent_t done = nullptr;           // every block of this job and its final state copy done (engine stream)
+  SolveState* final_state = nullptr;   // pinned
+  int checked = 0;                     // blocks whose head the worker has read
+  int k = 0;                           // seed iterations of those blocks
+  bool breakdown = false;
+  bool retired = false;                // worker: no longer in the batch
+  bool finished = false;               // guarded by the engine mutex
+};
+
+}  // namespace
+
+struct tem_engine {
+  int device = 0;
+  int max_jobs = tem::kMaxBatchJobs;
+  hipStream_t stream = nullptr;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv;       // wakes the worker: new jobs or stop
+  std::condition_variable done_cv;  // wakes submitters: a job finished
+  std::deque<EngineJob*> pending;
+  bool stop = false;
+  hipError_t error = hipSuccess;    // first HIP failure of the worker; every job then fails
+  static constexpr int kGens = 4;   // job tables in flight (a table is reused 4 generations later)
+  tem::BatchJob* d_tables = nullptr;
+  tem::BatchJob* h_tables = nullptr;  // pinned staging of the tables
+  tem::SolveHead* d_heads = nullptr;
+  tem::SolveHead* h_heads = nullptr;  // pinned, one set per block in flight
+  hipEvent_t head_ev[2] = {nullptr, nullptr};
+  // statistics (guarded by mu)
+  long long blocks = 0, job_blocks = 0;
+  int max_jobs_seen = 0, max_ctx_seen = 0;
+};
+
+namespace {
+
+constexpr int kEngineBlock = 64;  // seed iterations per batched block
+
+void engine_worker(tem_engine* E) {
+  (void)hipSetDevice(E->device);
+  constexpr int B = kEngineBlock;
+  struct Gen {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<EngineJob*> jobs;
+    ~Gen() {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+    }
+  };
+  std::vector<EngineJob*> active;
+  std::deque<std::pair<int, std::shared_ptr<Gen>>> inflight;
+  std::shared_ptr<Gen> cur;
+  int next_table = 0, parity = 0;
+  bool dirty = true;
+  hipError_t err = hipSuccess;
+  auto finish = [&](EngineJob* jb) {
+    // queued after every block issued so far, which includes the job's last one
+    SolveSlot& sl = jb->ctx->slots[jb->slot];
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(jb->final_state, sl.d_state, sizeof(SolveState), hipMemcpyDeviceToHost, E->stream);
+    if (err == hipSuccess) err = hipEventRecord(jb->done, E->stream);
+    jb->retired = true;
+    active.erase(std::remove(active.begin(), active.end(), jb), active.end());
+    dirty = true;
+    std::lock_guard<std::mutex> lk(E->mu);
+    jb->finished = true;
+  };
+  for (;;) {
+    std::vector<EngineJob*> fresh;
+    {
+      std::unique_lock<std::mutex> lk(E->mu);
+      E->cv.wait(lk, [&] { return E->stop || !E->pending.empty() || !active.empty() || !inflight.empty(); });
+      if (E->stop && E->pending.empty() && active.empty() && inflight.empty()) break;
+      while (!E->pending.empty() && (int)active.size() + (int)fresh.size() < E->max_jobs) {
+        fresh.push_back(E->pending.front());
+        E->pending.pop_front();
+      }
+      if (err != hipSuccess) E->error = err;
+    }
+    if (err != hipSuccess) {
+      // fail every job: nothing more is launched
+      std::lock_guard<std::mutex> lk(E->mu);
+      for (EngineJob* jb : fresh) jb->finished = true;
+      for (EngineJob* jb : active) jb->finished = true;
+      active.clear();
+      inflight.clear();
+      E->done_cv.notify_all();
+      continue;
+    }
+    for (EngineJob* jb : fresh) {
+      SolveSlot& sl = jb->ctx->slots[jb->slot];
+      const size_t n3 = jb->ctx->n3;
+      if (err == hipSuccess) err = hipStreamWaitEvent(E->stream, jb->ready, 0);
+      if (err == hipSuccess)
+        err = hipMemcpyAsync(sl.d_state, jb->init.get(), sizeof(SolveState), hipMemcpyHostToDevice, E->stream);
+      if (err == hipSuccess) {
+        const tem::Reduce red{(double*)sl.partials.p, jb->ctx->d_counters};
+        tem::launch_seed_init(jb->ctx->g, (const double*)sl.gvec.p, (double*)sl.R.p, (double*)sl.pbuf.p + n3, jb->Y,
+                              (double2*)sl.P.p, jb->J, red, sl.d_state, E->stream);
+        err = hipGetLastError();
+      }
+      active.push_back(jb);
+      dirty = true;
+    }
+    if (err != hipSuccess) continue;
+    if (!active.empty() && inflight.size() < 2) {
+      if (dirty) {
+        // the batch's job table and graph for the current set of jobs
+        auto gen = std::make_shared<Gen>();
+        gen->jobs = active;
+        const int n = (int)active.size();
+        const int slot = next_table;
+        next_table = (next_table + 1) % tem_engine::kGens;
+        tem::BatchJob* ht = E->h_tables + (size_t)slot * tem::kMaxBatchJobs;
+        tem::BatchJob* dt = E->d_tables + (size_t)slot * tem::kMaxBatchJobs;
+        int tiles = 0, bus = 0, maxJ = 1;
+        for (int i = 0; i < n; ++i) {
+          EngineJob* jb = active[i];
+          SolveSlot& sl = jb->ctx->slots[jb->slot];
+          tem::BatchJob& b = ht[i];
+          b = tem::BatchJob{};
+          b.g = jb->ctx->g;
+          b.dinv = jb->ctx->d_dinv;
+          b.s0 = jb->s0;
+          b.R = (double*)sl.R.p;
+          b.pbuf = (double*)sl.pbuf.p;
+          b.q = (double*)sl.q.p;
+          b.part_st = (double*)sl.partials.p;
+          b.part_up = (double*)sl.partials.p + tem::kReduceSlots;
+          b.st = sl.d_state;
+          b.Y = jb->Y;
+          b.P = (double2*)sl.P.p;
+          b.J = jb->J;
+          b.tile0 = tiles;
+          b.ntiles = tem::batch_tiles(b.g, &b.ntx, &b.nty);
+          b.bu0 = bus;
+          b.nbu = tem::block_update_blocks(b.g);
+          tiles += b.ntiles;
+          bus += b.nbu;
+          maxJ = std::max(maxJ, jb->J);
+        }
+        err = hipMemcpyAsync(dt, ht, n * sizeof(tem::BatchJob), hipMemcpyHostToDevice, E->stream);
+        if (err == hipSuccess) err = hipGraphCreate(&gen->graph, 0);
+        if (err == hipSuccess) {
+          tem::Sink k;
+          k.graph = gen->graph;
+          for (int l = 0; l < B; ++l) {
+            tem::launch_seed_stencil_batch(dt, n, tiles, B, l, k);
+            tem::launch_seed_update_batch(dt, n, B, l, k);
+          }
+          tem::launch_shift_block_batch(dt, n, maxJ, k);
+          tem::launch_block_update_batch(dt, n, bus, B, k);
+          tem::launch_gather_heads(dt, n, E->d_heads, k);
+          err = k.err;
+        }
+        if (err == hipSuccess) err = hipGraphInstantiate(&gen->exec, gen->graph, nullptr, nullptr, 0);
+        if (err != hipSuccess) continue;
+        cur = gen;
+        dirty = false;
+      }
+      const int n = (int)cur->jobs.size();
+      err = hipGraphLaunch(cur->exec, E->stream);
+      if (err == hipSuccess)
+        err = hipMemcpyAsync(E->h_heads + (size_t)parity * tem::kMaxBatchJobs, E->d_heads,
+                             n * sizeof(tem::SolveHead), hipMemcpyDeviceToHost, E->stream);
+      if (err == hipSuccess) err = hipEventRecord(E->head_ev[parity], E->stream);
+      if (err != hipSuccess) continue;
+      inflight.emplace_back(parity, cur);
+      parity ^= 1;
+      {
+        std::lock_guard<std::mutex> lk(E->mu);
+        std::vector<const tem_ctx*> ctxs;
+        for (EngineJob* jb : cur->jobs)
+          if (std::find(ctxs.begin(), ctxs.end(), jb->ctx) == ctxs.end()) ctxs.push_back(jb->ctx);
+        ++E->blocks;
+        E->job_blocks += n;
+        E->max_jobs_seen = std::max(E->max_jobs_seen, n);
+        E->max_ctx_seen = std::max(E->max_ctx_seen, (int)ctxs.size());
+      }
+      continue;
+    }
+    // read the heads of the oldest block in flight
+    const int par = inflight.front().first;
+    std::shared_ptr<Gen> gen = inflight.front().second;
+    inflight.pop_front();
+    err = hipEventSynchronize(E->head_ev[par]);
+    if (err != hipSuccess) continue;
+    bool any = false;
+    for (size_t i = 0; i < gen->jobs.size(); ++i) {
+      EngineJob* jb = gen->jobs[i];
+      if (jb->retired) continue;
+      const tem::SolveHead& h = E->h_heads[(size_t)par * tem::kMaxBatchJobs + i];
+      ++jb->checked;
+      jb->k = jb->checked * B;
+      int n_active = 0;
+      for (int j = 0; j < jb->J; ++j) n_active += h.active[j];
+      if (h.breakdown) jb->breakdown = true;
+      if (h.breakdown || n_active == 0 || jb->k >= jb->max_iter) {
+        finish(jb);
+        any = true;
+      }
+    }
+    if (any) E->done_cv.notify_all();
+  }
+  // drain: nothing in flight is left behind
+  (void)hipStreamSynchronize(E->stream);
+}
+
+// The multi-shift solves of multishift_solve, submitted to the context's
+// engine (FP64 directions, 64-iteration blocks); same inputs and outputs.
+int engine_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const std::vector<double>& shifts_im, double s0,
+                 const tem_solve_opts& o, int njobs, double2* const* Ys, SolveState* states, double& seconds) {
+  tem_engine* E = ctx->engine;
+  const int J = (int)shifts_re.size();
+  constexpr int B = kEngineBlock;
+  const size_t n3 = ctx->n3;
+  int rc;
+  if ((rc = ensure_slots(ctx, njobs))) return rc;
+  for (int i = 0; i < njobs; ++i) {
+    SolveSlot& sl = ctx->slots[i];
+    if ((rc = ensure(ctx, sl.R, (size_t)B * n3 * sizeof(double))) ||
+        (rc = ensure(ctx, sl.pbuf, 2 * n3 * sizeof(double))) || (rc = ensure(ctx, sl.q, n3 * sizeof(double))) ||
+        (rc = ensure(ctx, sl.P, (size_t)J * n3 * sizeof(double2))) ||
+        (rc = ensure(ctx, sl.partials, 2 * (size_t)tem::kReduceSlots * sizeof(double))))
+      return rc;
+  }
+  std::vector<std::unique_ptr<EngineJob>> jobs(njobs);
+  auto cleanup = [&]() {
+    for (auto& jb : jobs) {
+      if (!jb) continue;
+      if (jb->ready) (void)hipEventDestroy(jb->ready);
+      if (jb->done) (void)hipEventDestroy(jb->done);
+      if (jb->final_state) (void)hipHostFree(jb->final_state);
+    }
+  };
+  for (int i = 0; i < njobs; ++i) {
+    jobs[i].reset(new EngineJob());
+    EngineJob& jb = *jobs[i];
+    jb.ctx = ctx;
+    jb.slot = i;
+    jb.Y = Ys[i];
+    jb.J = J;
+    jb.s0 = s0;
+    jb.max_iter = o.max_iter;
+    jb.init.reset(new SolveState());
+    SolveState& hs = *jb.init;
+    std::memset(&hs, 0, sizeof(SolveState));
+    hs.J = J;
+    hs.B = B;
+    hs.tol2 = o.rtol * o.rtol;
+    for (int j = 0; j < J; ++j) {
+      hs.sig_re[j] = shifts_re[j] - s0;
+      hs.sig_im[j] = shifts_im[j];
+      hs.z_re[j] = hs.zp_re[j] = 1.0;
+      hs.active[j] = 1;
+      hs.apply[j] = 1;
+      hs.cf[j][0][0] = 1.0;
+    }
+    hipError_t e = hipEventCreateWithFlags(&jb.ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&jb.done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&jb.final_state, sizeof(SolveState), hipHostMallocDefault);
+    // the right-hand side and the cleared buffers were written on the library stream
+    if (e == hipSuccess) e = hipEventRecord(jb.ready, ctx->work);
+    if (e != hipSuccess) {
+      cleanup();
+      return fail(ctx, TEM_EHIP, std::string("engine submit: ") + hipGetErrorString(e));
+    }
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  {
+    std::unique_lock<std::mutex> lk(E->mu);
+    for (auto& jb : jobs) E->pending.push_back(jb.get());
+    E->cv.notify_all();
+    E->done_cv.wait(lk, [&] {
+      for (auto& jb : jobs)
+        if (!jb->finished) return false;
+      return true;
+    });
+  }
+  hipError_t e = E->error;
+  bool breakdown = false;
+  for (int i = 0; i < njobs && e == hipSuccess; ++i) {
+    e = hipEventSynchronize(jobs[i]->done);
+    if (e != hipSuccess) break;
+    states[i] = *jobs[i]->final_state;
+    states[i].k = jobs[i]->k;
+    states[i].breakdown = jobs[i]->breakdown ? 1 : 0;
+    breakdown |= jobs[i]->breakdown;
+    e = hipStreamWaitEvent(ctx->work, jobs[i]->done, 0);  // later work on the library stream reads Y
+  }
+  seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  cleanup();
+  if (e != hipSuccess) return fail(ctx, TEM_EHIP, std::string("solve engine: ") + hipGetErrorString(e));
+  if (breakdown) return fail(ctx, TEM_EBREAKDOWN, "Krylov breakdown in the shared recurrence");
+  for (int i = 0; i < njobs; ++i)
+    for (int j = 0; j < J; ++j)
+      if (states[i].active[j]) return fail(ctx, TEM_ENOCONV, "max_iter reached before every shift converged");
+  return TEM_OK;
+}
+
 // njobs independent multi-shift solves (all J shifts each), job i in slot i
 // with its right-hand side g = M^{-1/2} f already in slots[i].gvec (written on
 // the library stream).  Ys[i] receives the scaled solutions y_j = M^{1/2} x_j
-// (node-padded, complex; V = double2 for the FP64 path, float2 for the
-// complex FP32 shift vectors of precision 1); states[i] the final solver state.
-// Each job runs on its slot's stream; the host replays every active job's
-// block graph before it waits for any of them, so their kernels overlap.
-template <typename V>
+// (node-padded, complex FP64); the per-shift search directions p_j are kept
+// in PV (double2 for the FP64 path, float2 for precision 1); states[i] the
+// final solver state.  Each job runs on its slot's stream; the host replays
+// every active job's block graph before it waits for any of them, so their
+// kernels overlap.
+template <typename PV>
 int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const std::vector<double>& shifts_im,
-                     double s0, const tem_solve_opts& o, int njobs, V* const* Ys, SolveState* states,
+                     double s0, const tem_solve_opts& o, int njobs, double2* const* Ys, SolveState* states,
                      double& seconds) {
+  if constexpr (std::is_same<PV, double2>::value) {
+    if (ctx->engine) return engine_solve(ctx, shifts_re, shifts_im, s0, o, njobs, Ys, states, seconds);
+  }
   const int J = (int)shifts_re.size();
   const int B = block_length(o.block);
   const GridArgs& g = ctx->g;
@@ -300,7 +641,7 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     }
     if (timed) (void)hipEventRecord(ev[4 * B], st.stream);
     tem::launch_shift_block(g, J, red, sl.d_state, st);
-    tem::launch_block_update(g, R, Ys[i], (V*)sl.P.p, J, B, sl.d_state, st);
+    tem::launch_block_update(g, R, Ys[i], (PV*)sl.P.p, J, B, sl.d_state, st);
     if (timed) (void)hipEventRecord(ev[4 * B + 1], st.stream);
   };
   struct Run {
@@ -340,7 +681,7 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     if (se == hipSuccess) {
       const tem::Reduce red{(double*)sl.partials.p, ctx->d_counters};
       tem::launch_seed_init(g, (const double*)sl.gvec.p, (double*)sl.R.p, (double*)sl.pbuf.p + n3, Ys[i],
-                            (V*)sl.P.p, J, red, sl.d_state, st);
+                            (PV*)sl.P.p, J, red, sl.d_state, st);
       se = hipGetLastError();
     }
     if (se != hipSuccess) {
@@ -488,9 +829,12 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
 // Batched COCG on (A + s_j) mu_j = h_j for the J shifts in ctx->sh, vectors
 // of V storage (Mu, Rr, P0, P1, Q: J node-padded vectors each); stops shift j
 // when |r_j| <= rtol |h_j|.  Shifts with h_j = 0 stay inactive (mu_j = 0).
+// With stall > 0, shift j is also stopped once its recursive residual has not
+// fallen by 10% over `stall` iterations (checked every 32 iterations), so
+// that a correction which stagnates cannot run to its cap.
 template <typename V>
 int cocg_solve(tem_ctx* ctx, int J, const double2* H, V* Mu, V* Rr, V* P0, V* P1, V* Q, double rtol, int max_iter,
-               tem::CocgState& hs, int& iterations, const int* caps = nullptr) {
+               tem::CocgState& hs, int& iterations, const int* caps = nullptr, int stall = 0) {
   hipStream_t st = ctx->work;
   int rc;
   if ((rc = ensure(ctx, ctx->cst, tem::cocg_state_bytes())) ||
@@ -511,6 +855,8 @@ int cocg_solve(tem_ctx* ctx, int J, const double2* H, V* Mu, V* Rr, V* P0, V* P1
   iterations = 0;
   const auto t0 = std::chrono::steady_clock::now();
   double next_report = 10.0;
+  std::vector<double> best(J, -1.0);  // smallest |r_j|^2 that was a 10% reduction, and when
+  std::vector<int> best_it(J, 0), cap_now(hs.cap, hs.cap + J);
   while (it < max_iter) {
     for (int i = 0; i < chunk; ++i, ++it) {
       V* Pold = (it & 1) ? P1 : P0;
@@ -526,6 +872,25 @@ int cocg_solve(tem_ctx* ctx, int J, const double2* H, V* Mu, V* Rr, V* P0, V* P1
     iterations = it;
     if (hs.breakdown) return fail(ctx, TEM_EBREAKDOWN, "COCG breakdown");
     if (hs.n_active == 0) break;
+    if (stall > 0) {
+      bool changed = false;
+      for (int j = 0; j < J; ++j) {
+        if (!hs.active[j]) continue;
+        if (best[j] < 0.0 || hs.rn2[j] <= 0.81 * best[j]) {
+          best[j] = hs.rn2[j];
+          best_it[j] = hs.iters[j];
+        } else if (hs.iters[j] - best_it[j] >= stall && cap_now[j] > hs.iters[j] + 1) {
+          cap_now[j] = hs.iters[j] + 1;  // the next update stops it
+          changed = true;
+        }
+      }
+      if (changed) {
+        tem::CocgState* dst = (tem::CocgState*)ctx->cst.p;
+        e = hipMemcpyAsync(dst->cap, cap_now.data(), J * sizeof(int), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);  // cap_now is host memory read by the copy
+        if (e != hipSuccess) return fail(ctx, TEM_EHIP, std::string("COCG: ") + hipGetErrorString(e));
+      }
+    }
     if (verbose()) {
       const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       if (el >= next_report) {
@@ -538,6 +903,231 @@ int cocg_solve(tem_ctx* ctx, int J, const double2* H, V* Mu, V* Rr, V* P0, V* P1
   bool capped = hs.n_active > 0;
   for (int j = 0; j < J; ++j) capped |= hs.iters[j] >= hs.cap[j] && hs.rn2[j] > hs.tol2 * hs.hn2[j];
   return capped ? fail(ctx, TEM_ENOCONV, "COCG did not reach rtol within its iteration cap") : TEM_OK;
+}
+
+// Two-pass form (opts.method 1) for the source whose right-hand side is in
+// slot i: pass 1 runs the seed recurrence with the shift-block convergence
+// test and records alpha_k, beta_k, (r_{k+1}, r_{k+1}) and q_r . (M^-1/2 r_k);
+// the host replays each shift's recurrence (the k_shift_block formulas) to
+// get y_j = sum_k gamma_jk r_k, gamma_jk = zeta_jk S_jk with
+// S_jk = alpha^s_jk + beta^s_jk S_j,k+1, and w_kt = Re sum_j c_jt gamma_jk;
+// data[t][r] = sum_k (q_r . M^-1/2 r_k) w_kt.  With fields, pass 2 reruns the
+// seed (the same kernels and state, so the same residuals bit for bit) and
+// accumulates U = sum_k r_k w_k^T block by block on MFMA.
+int lanczos_source(tem_ctx* ctx, int i, const std::vector<double>& shifts_re, const std::vector<double>& shifts_im,
+                   double s0, const tem_solve_opts& o, int T, const double* c, int n_rx, double* data, double* fields,
+                   SolveState& fin, double& secs) {
+  const int J = (int)shifts_re.size();
+  const int B = block_length(o.block);
+  const GridArgs& g = ctx->g;
+  const size_t n3 = ctx->n3;
+  hipStream_t st = ctx->work;
+  int rc;
+  SolveSlot& sl = ctx->slots[i];
+  if ((rc = ensure(ctx, sl.R, (size_t)B * n3 * sizeof(double))) ||
+      (rc = ensure(ctx, sl.pbuf, 2 * n3 * sizeof(double))) || (rc = ensure(ctx, sl.q, n3 * sizeof(double))) ||
+      (rc = ensure(ctx, sl.partials, 2 * (size_t)tem::kReduceSlots * sizeof(double))))
+    return rc;
+  const int nrx = std::max(n_rx, 1);
+  DevBuf hqd, Wd, Ud;
+  double* hq_pin = nullptr;  // pinned: the receiver values of the two blocks in flight
+  auto cleanup = [&]() {
+    release(hqd);
+    release(Wd);
+    release(Ud);
+    if (hq_pin) (void)hipHostFree(hq_pin);
+  };
+  if ((rc = ensure(ctx, hqd, (size_t)B * nrx * sizeof(double)))) return rc;
+  if (hipHostMalloc((void**)&hq_pin, 2 * (size_t)B * nrx * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    cleanup();
+    return fail(ctx, TEM_ENOMEM, "pinned receiver buffer");
+  }
+  std::unique_ptr<SolveState> hs(new SolveState());
+  std::memset(hs.get(), 0, sizeof(SolveState));
+  hs->J = J;
+  hs->B = B;
+  hs->tol2 = o.rtol * o.rtol;
+  for (int j = 0; j < J; ++j) {
+    hs->sig_re[j] = shifts_re[j] - s0;
+    hs->sig_im[j] = shifts_im[j];
+    hs->z_re[j] = hs->zp_re[j] = 1.0;
+    hs->active[j] = 1;
+    hs->apply[j] = 1;
+    hs->cf[j][0][0] = 1.0;
+  }
+  // the leading part of the state up to and including this block's history
+  const size_t hist_bytes = offsetof(SolveState, carry_alpha);
+  static_assert(offsetof(SolveState, carry_alpha) <= kHeadStride, "history head fits the pinned buffer");
+  const tem::Reduce red{(double*)sl.partials.p, ctx->d_counters};
+  double* R = (double*)sl.R.p;
+  double* pb = (double*)sl.pbuf.p;
+  double* q = (double*)sl.q.p;
+  const int* rxp = (const int*)ctx->rx.p;
+  auto init = [&]() -> hipError_t {
+    hipError_t e = hipMemcpyAsync(sl.d_state, hs.get(), sizeof(SolveState), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    tem::launch_seed_init(g, (const double*)sl.gvec.p, R, pb + n3, (double2*)nullptr, (double2*)nullptr, 0, red,
+                          sl.d_state, st);
+    return hipGetLastError();
+  };
+  // the seed kernels of one block plus the shift recurrences (convergence and
+  // the iteration count); `extra` appends the pass's own kernel
+  auto build = [&](hipGraph_t* gr, hipGraphExec_t* ex, const std::function<void(tem::Sink&)>& extra) -> hipError_t {
+    hipError_t e = hipGraphCreate(gr, 0);
+    if (e != hipSuccess) return e;
+    tem::Sink k;
+    k.graph = *gr;
+    for (int l = 0; l < B; ++l) {
+      tem::launch_seed_stencil(g, R + (size_t)l * n3, pb + (size_t)((l + 1) & 1) * n3, pb + (size_t)(l & 1) * n3, q,
+                               ctx->d_dinv, s0, red, sl.d_state, l, k);
+      tem::launch_seed_update(g, R + (size_t)l * n3, q, R + (size_t)((l + 1) % B) * n3, red, sl.d_state, l, k);
+    }
+    tem::launch_shift_block(g, J, red, sl.d_state, k);
+    extra(k);
+    if (k.err != hipSuccess) return k.err;
+    return hipGraphInstantiate(ex, *gr, nullptr, nullptr, 0);
+  };
+  hipGraph_t g1 = nullptr, g2 = nullptr;
+  hipGraphExec_t x1 = nullptr, x2 = nullptr;
+  auto drop = [&]() {
+    for (hipGraphExec_t x : {x1, x2})
+      if (x) (void)hipGraphExecDestroy(x);
+    for (hipGraph_t gg : {g1, g2})
+      if (gg) (void)hipGraphDestroy(gg);
+  };
+  const auto t0 = std::chrono::steady_clock::now();
+  // ---- pass 1
+  std::vector<double> ha, hb, hr, hq;  // alpha_k, beta_k, (r_{k+1}, r_{k+1}); q_r . M^-1/2 r_k
+  hipError_t e = init();
+  if (e == hipSuccess && n_rx > 0) {
+    tem::Sink d;
+    d.stream = st;
+    tem::launch_ring_receivers(g, R, B, ctx->d_dinv, rxp, n_rx, ctx->ks, (double*)hqd.p, 1, d);
+    hq.resize(n_rx);
+    e = hipMemcpyAsync(hq.data(), hqd.p, n_rx * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  if (e == hipSuccess)
+    e = build(&g1, &x1, [&](tem::Sink& k) {
+      if (n_rx > 0) tem::launch_ring_receivers(g, R, B, ctx->d_dinv, rxp, n_rx, ctx->ks, (double*)hqd.p, 0, k);
+    });
+  int launched = 0, checked = 0;
+  bool done = false, breakdown = false;
+  while (e == hipSuccess && !done) {
+    while (e == hipSuccess && launched - checked < 2 && (long long)launched * B < o.max_iter) {
+      const int h = launched & 1;
+      e = hipGraphLaunch(x1, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync((char*)sl.head + h * kHeadStride, sl.d_state, hist_bytes, hipMemcpyDeviceToHost, st);
+      // the block's receiver values, copied before the next block overwrites them
+      if (e == hipSuccess && n_rx > 0)
+        e = hipMemcpyAsync(hq_pin + (size_t)h * B * n_rx, hqd.p, (size_t)B * n_rx * sizeof(double),
+                           hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipEventRecord(sl.head_ev[h], st);
+      ++launched;
+    }
+    if (e != hipSuccess || launched == checked) break;
+    const int h = checked & 1;
+    e = hipEventSynchronize(sl.head_ev[h]);
+    if (e != hipSuccess) break;
+    const SolveState* hd = (const SolveState*)((const char*)sl.head + h * kHeadStride);
+    ha.insert(ha.end(), hd->alpha_h, hd->alpha_h + B);
+    hb.insert(hb.end(), hd->beta_h, hd->beta_h + B);
+    hr.insert(hr.end(), hd->rr_h, hd->rr_h + B);
+    if (n_rx > 0) hq.insert(hq.end(), hq_pin + (size_t)h * B * n_rx, hq_pin + (size_t)(h + 1) * B * n_rx);
+    ++checked;
+    int n_active = 0;
+    for (int j = 0; j < J; ++j) n_active += hd->active[j];
+    if (hd->breakdown) breakdown = true;
+    if (hd->breakdown || n_active == 0 || (long long)checked * B >= o.max_iter) done = true;
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&fin, sl.d_state, sizeof(SolveState), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(st);
+    drop();
+    cleanup();
+    return fail(ctx, TEM_EHIP, std::string("two-pass solve: ") + hipGetErrorString(e));
+  }
+  fin.k = checked * B;
+  fin.breakdown = breakdown ? 1 : 0;
+  // ---- host: the shifted recurrences and the channel weights w_kt
+  int kmax = 0;
+  for (int j = 0; j < J; ++j) kmax = std::max(kmax, fin.iters[j]);
+  const int nblk = (kmax + B - 1) / B;
+  const size_t rows = (size_t)nblk * B + 1;
+  std::vector<double> W(rows * T, 0.0);
+  using cd = std::complex<double>;
+  for (int j = 0; j < J; ++j) {
+    const int K = fin.iters[j];
+    const cd sig(hs->sig_re[j], hs->sig_im[j]);
+    std::vector<cd> zeta(K + 1), as(K), bs(K);
+    cd z(1.0, 0.0), zp(1.0, 0.0);
+    for (int k = 0; k < K; ++k) {
+      const double a_k = ha[k], b_k = hb[k];
+      const double a_km1 = k ? ha[k - 1] : 1.0, b_km1 = k ? hb[k - 1] : 0.0;
+      const cd num = a_km1 * z * zp;
+      const cd den = (a_k * b_km1) * (zp - z) + a_km1 * zp * (1.0 + sig * a_k);
+      const cd zn = num / den;
+      const cd ratio = a_km1 * zp / den;
+      zeta[k] = z;
+      as[k] = a_k * ratio;
+      bs[k] = b_k * ratio * ratio;
+      zp = z;
+      z = zn;
+    }
+    cd S(0.0, 0.0);
+    for (int k = K - 1; k >= 0; --k) {
+      S = as[k] + bs[k] * S;
+      const cd gamma = zeta[k] * S;
+      for (int t = 0; t < T; ++t) {
+        const cd cjt(c[2 * ((size_t)j * T + t)], c[2 * ((size_t)j * T + t) + 1]);
+        W[(size_t)k * T + t] += (cjt * gamma).real();
+      }
+    }
+  }
+  // receivers: data[t][r] = sum_k hq[k][r] w_kt
+  if (n_rx > 0) {
+    std::fill(data, data + (size_t)T * n_rx, 0.0);
+    const size_t kk = std::min((size_t)kmax, hq.size() / n_rx);
+    for (size_t k = 0; k < kk; ++k)
+      for (int r = 0; r < n_rx; ++r) {
+        const double v = hq[k * n_rx + r];
+        for (int t = 0; t < T; ++t) data[(size_t)t * n_rx + r] += v * W[k * T + t];
+      }
+  }
+  // ---- pass 2: the fields
+  if (fields) {
+    if ((rc = ensure(ctx, Wd, rows * T * sizeof(double))) || (rc = ensure(ctx, Ud, (size_t)T * n3 * sizeof(double)))) {
+      drop();
+      cleanup();
+      return rc;
+    }
+    e = hipMemcpyAsync(Wd.p, W.data(), rows * T * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = init();
+    if (e == hipSuccess) {
+      tem::launch_ring_contract_init(g, R, (const double*)Wd.p, T, (double*)Ud.p, st);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+      e = build(&g2, &x2, [&](tem::Sink& k) {
+        tem::launch_ring_contract(g, R, B, (const double*)Wd.p, T, (double*)Ud.p, sl.d_state, k);
+      });
+    for (int b = 0; b < nblk && e == hipSuccess; ++b) e = hipGraphLaunch(x2, st);
+    if (e == hipSuccess) {
+      tem::launch_ring_fields(g, (const double*)Ud.p, T, ctx->d_dinv, fields, rxp, 0, ctx->ks, nullptr, st);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  drop();
+  cleanup();
+  secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (e != hipSuccess) return fail(ctx, TEM_EHIP, std::string("two-pass solve: ") + hipGetErrorString(e));
+  if (breakdown) return fail(ctx, TEM_EBREAKDOWN, "Krylov breakdown in the shared recurrence");
+  for (int j = 0; j < J; ++j)
+    if (fin.active[j]) return fail(ctx, TEM_ENOCONV, "max_iter reached before every shift converged");
+  return TEM_OK;
 }
 
 }  // namespace
@@ -691,6 +1281,70 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
   }
   if ((rc = order_after_caller(ctx))) return rc;
   hipStream_t st = ctx->work;
+  if (o.method == 1) {
+    if (o.precision != 0 || o.keep_solutions)
+      return fail(ctx, TEM_EINVAL, "the two-pass form (method 1) is FP64 only and keeps no solutions");
+    // memory-lean two-pass form: no per-shift vectors; sources one at a time
+    if ((rc = ensure_slots(ctx, 1)) || (rc = ensure(ctx, ctx->slots[0].gvec, ctx->n3 * sizeof(double))) ||
+        (rc = ensure(ctx, ctx->f, ctx->n3 * sizeof(double))) ||
+        (rc = ensure(ctx, ctx->rx, 2 * (size_t)std::max(n_rx, 1) * sizeof(int))))
+      return rc;
+    std::vector<int> rxi(2 * std::max(n_rx, 1), 0);
+    for (int r = 0; r < n_rx; ++r) {
+      rxi[2 * r] = rx[r].i;
+      rxi[2 * r + 1] = rx[r].j;
+    }
+    HIPCHK(ctx, hipMemcpyAsync(ctx->rx.p, rxi.data(), rxi.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    // the shifts on the device, for an adjoint after this forward
+    if ((rc = ensure(ctx, ctx->sh, 4 * (size_t)TEM_MAX_SHIFTS * sizeof(double)))) return rc;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->sh.p, sre.data(), J * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync((double*)ctx->sh.p + TEM_MAX_SHIFTS, sim.data(), J * sizeof(double),
+                               hipMemcpyHostToDevice, st));
+    tem_stats S{};
+    S.n_shifts = J;
+    S.converged = 1;
+    int status = TEM_OK;
+    std::vector<double> fs(ctx->n3);
+    std::unique_ptr<SolveState> fin(new SolveState());
+    for (int s = 0; s < n_src; ++s) {
+      loop_source(ctx, src[s], fs);
+      HIPCHK(ctx, hipMemcpyAsync(ctx->f.p, fs.data(), ctx->n3 * sizeof(double), hipMemcpyHostToDevice, st));
+      tem::launch_scale(ctx->n3, ctx->d_dinv, (const double*)ctx->f.p, (double*)ctx->slots[0].gvec.p, st);
+      HIPCHK(ctx, hipGetLastError());
+      double secs = 0.0;
+      const int r = lanczos_source(ctx, 0, sre, sim, s0, o, T, c, n_rx, n_rx > 0 ? data + (size_t)s * T * n_rx : nullptr,
+                                   fields ? fields + (size_t)s * T * ctx->nstore : nullptr, *fin, secs);
+      if (r == TEM_ENOCONV) {
+        S.converged = 0;
+        status = r;
+      } else if (r != TEM_OK) {
+        return r;
+      }
+      S.iterations = fin->k;
+      for (int j = 0; j < J; ++j) {
+        S.iters_per_shift[j] = fin->iters[j];
+        S.est_res[j] = fin->est[j] / std::sqrt(fin->rr0);
+        S.true_res[j] = -1.0;
+        S.unknown_updates += (double)ctx->nunk * fin->iters[j];
+      }
+    }
+    ctx->fwd_valid = false;
+    ctx->fwd_meta = true;
+    ctx->fwd_J = J;
+    ctx->fwd_T = T;
+    ctx->fwd_nsrc = n_src;
+    ctx->fwd_nrx = n_rx;
+    ctx->fwd_xi.assign(xi, xi + 2 * J);
+    ctx->fwd_c.assign(c, c + 2 * (size_t)J * T);
+    ctx->fwd_rx.assign(rx, rx + n_rx);
+    ctx->fwd_src.assign(src, src + n_src);
+    ctx->fwd_opts = o;
+    ctx->fwd_opts.method = 0;  // an adjoint after this forward recomputes the solutions (FP64, method 0)
+    ctx->fwd_s0 = s0;
+    S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (stats) *stats = S;
+    return status;
+  }
   const size_t ysz = (size_t)J * ctx->n3 * sizeof(double2);
   const int nconc = std::min(n_src, kMaxConcurrentSolves);  // sources solved at once
   const int nY = o.keep_solutions ? n_src : nconc;
@@ -700,7 +1354,6 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
   if ((rc = ensure_slots(ctx, nconc))) return rc;
   for (int i = 0; i < nconc; ++i) {
     if ((rc = ensure(ctx, ctx->slots[i].gvec, ctx->n3 * sizeof(double)))) return rc;
-    if (o.precision == 1 && (rc = ensure(ctx, ctx->slots[i].y32, (size_t)J * ctx->n3 * sizeof(float2)))) return rc;
   }
   if ((rc = ensure(ctx, ctx->P, (size_t)J * ctx->n3 * sizeof(double2)))) return rc;
   if ((rc = ensure(ctx, ctx->gc, ctx->n3 * sizeof(double2)))) return rc;
@@ -744,21 +1397,17 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
     }
     double secs = 0.0;
     int r;
+    std::vector<double2*> ys(nb);
+    for (int i = 0; i < nb; ++i) ys[i] = (double2*)ctx->Y[o.keep_solutions ? s_first + i : i].p;
     if (o.precision == 1) {
-      // sweeps with complex FP32 shift vectors, then y_j widened to FP64
+      // the sweep accumulates y_j in FP64 and keeps only the search directions
+      // p_j in complex FP32; it stops at the recursive tolerance kSweepTolFP32
+      // and the FP64 residual refinement below takes over
       tem_solve_opts o32 = o;
-      o32.rtol = std::max(o.rtol, kSweepTolFP32);
-      std::vector<float2*> ys(nb);
-      for (int i = 0; i < nb; ++i) ys[i] = (float2*)ctx->slots[i].y32.p;
-      r = multishift_solve(ctx, sre, sim, s0, o32, nb, ys.data(), states.data(), secs);
-      if (r == TEM_OK || r == TEM_ENOCONV)
-        for (int i = 0; i < nb; ++i)
-          tem::launch_accumulate(ctx->g, J, ys[i], (double2*)ctx->Y[o.keep_solutions ? s_first + i : i].p, 0, 0,
-                                 st);
+      o32.rtol = kSweepTolFP32;
+      r = multishift_solve<float2>(ctx, sre, sim, s0, o32, nb, ys.data(), states.data(), secs);
     } else {
-      std::vector<double2*> ys(nb);
-      for (int i = 0; i < nb; ++i) ys[i] = (double2*)ctx->Y[o.keep_solutions ? s_first + i : i].p;
-      r = multishift_solve(ctx, sre, sim, s0, o, nb, ys.data(), states.data(), secs);
+      r = multishift_solve<double2>(ctx, sre, sim, s0, o, nb, ys.data(), states.data(), secs);
     }
     if (r == TEM_ENOCONV) {
       S.converged = 0;
@@ -800,10 +1449,13 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
         // FP64 residual refinement: (A + s_j) d_j = rho_j by batched COCG with
         // complex FP32 vectors to kRefinePassTol, then the minimal-residual step
         // y_j += omega_j d_j, omega_j = (w_j, rho_j) / (w_j, w_j), w_j = (A + s_j) d_j
-        // in FP64, so no pass raises a shift's FP64 residual.  Each shift starts
-        // with a COCG budget of twice the sweep's iterations; a shift whose
-        // residual falls by less than 10% gets half its budget next pass and is no
-        // longer refined once that budget is below 32 iterations.
+        // in FP64, so no pass raises a shift's FP64 residual.  Every pass is
+        // bounded: at most kRefinePassCap COCG iterations per shift (later passes
+        // at most 16x what the previous one took, and at least 2048), and a shift
+        // whose correction residual has not fallen by 10% over kRefineStall
+        // iterations stops early.  A shift whose FP64 residual falls by less than
+        // 10% in a pass has reached what FP32 corrections can do and is not
+        // refined further.
         auto rel = [&](int j) { return std::sqrt(true2[j] / hs.rr0); };
         auto worst = [&]() {
           double w = 0.0;
@@ -811,7 +1463,7 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
           return w;
         };
         std::vector<char> stalled(J, 0);
-        std::vector<int> caps(J, std::min(o.max_iter, 2 * std::max(hs.k, 256)));
+        std::vector<int> caps(J, std::min(o.max_iter, kRefinePassCap));
         const int nbd = tem::dot_shifts_blocks(ctx->g);
         int passes = 0;
         while (passes < o.refine_max) {
@@ -832,7 +1484,7 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
           int its = 0;
           const int cap = *std::max_element(caps.begin(), caps.end());
           int r2 = cocg_solve(ctx, J, (const double2*)ctx->P.p, v, v + vn, v + 2 * vn, v + 3 * vn, v + 4 * vn,
-                              kRefinePassTol, cap, cs, its, caps.data());
+                              kRefinePassTol, cap, cs, its, caps.data(), kRefineStall);
           if (r2 != TEM_OK && r2 != TEM_ENOCONV) return r2;
           for (int j = 0; j < J; ++j) S.unknown_updates += (double)ctx->nunk * cs.iters[j];
           // a later pass of shift j may take up to 16x the iterations of this
@@ -871,8 +1523,7 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
           for (int j = 0; j < J; ++j)
             if (((todo >> j) & 1ull) && !(true2[j] < 0.81 * before[j])) {
               ++slow;
-              caps[j] /= 2;
-              if (caps[j] < 32) stalled[j] = 1;
+              stalled[j] = 1;
             }
           if (verbose())
             fprintf(stderr, "[tem] refinement pass %d: %d COCG iterations, %d shifts reduced by < 10%%, max scaled "
@@ -985,7 +1636,12 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
   int rc;
   if ((rc = order_after_caller(ctx))) return rc;
   hipStream_t st = ctx->work;
-  const tem_solve_opts& o = ctx->fwd_opts;
+  // the adjoint solves are FP64, to the FP64 default after a precision-1 forward
+  tem_solve_opts o = ctx->fwd_opts;
+  if (o.precision == 1) {
+    o.precision = 0;
+    o.rtol = 1e-12;
+  }
   const size_t vb = (size_t)J * ctx->n3 * sizeof(double2);
   DevBuf H, Mu, Rr, Pb, Q, z, gd, gam, cst;
   auto cleanup = [&]() {
@@ -1026,6 +1682,14 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
     if (e != hipSuccess) break;
     // forward solutions x_j of source s: stored, or recomputed now (one more
     // FP64 multi-shift solve; only one source's solutions are held at a time)
+    if (!ctx->fwd_valid) {
+      // room for one source's solutions (a two-pass forward holds none)
+      if (ctx->Y.empty()) ctx->Y.resize(1);
+      if ((rc = ensure(ctx, ctx->Y[0], (size_t)J * ctx->n3 * sizeof(double2)))) {
+        cleanup();
+        return rc;
+      }
+    }
     double2* Ys = (double2*)ctx->Y[ctx->fwd_valid ? s : 0].p;
     if (!ctx->fwd_valid) {
       std::vector<double> fsrc(ctx->n3), sre(J), sim(J);
@@ -1041,12 +1705,10 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
       e = hipMemcpyAsync(ctx->f.p, fsrc.data(), ctx->n3 * sizeof(double), hipMemcpyHostToDevice, st);
       if (e != hipSuccess) break;
       tem::launch_scale(ctx->n3, ctx->d_dinv, (const double*)ctx->f.p, (double*)ctx->slots[0].gvec.p, st);
-      tem_solve_opts of = o;  // an FP64 solve, to the FP64 default when the forward was precision 1
-      if (of.precision == 1) of.rtol = 1e-12;
-      of.precision = 0;
+      const tem_solve_opts& of = o;  // an FP64 solve (o is FP64 here)
       SolveState fst;
       double secs = 0.0;
-      const int r1 = multishift_solve(ctx, sre, sim, ctx->fwd_s0, of, 1, &Ys, &fst, secs);
+      const int r1 = multishift_solve<double2>(ctx, sre, sim, ctx->fwd_s0, of, 1, &Ys, &fst, secs);
       if (r1 == TEM_ENOCONV) S.converged = 0;
       else if (r1 != TEM_OK) {
         cleanup();
@@ -1089,7 +1751,7 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
         std::vector<double2*> ys(nb);
         for (int i = 0; i < nb; ++i) ys[i] = (double2*)H.p + (size_t)i * J * ctx->n3;
         double secs = 0.0;
-        int r2 = multishift_solve(ctx, sre, sim, ctx->fwd_s0, o, nb, ys.data(), states.data(), secs);
+        int r2 = multishift_solve<double2>(ctx, sre, sim, ctx->fwd_s0, o, nb, ys.data(), states.data(), secs);
         if (r2 == TEM_ENOCONV) S.converged = 0;
         else if (r2 != TEM_OK) {
           cleanup();
@@ -1153,6 +1815,158 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
   S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   if (stats) *stats = S;
   return S.converged ? TEM_OK : fail(ctx, TEM_ENOCONV, "adjoint COCG did not reach rtol within max_iter");
+}
+
+int tem_jacobian_apply(tem_ctx* ctx, const double* dm, double* ddata, tem_stats* stats) {
+  auto t_start = std::chrono::steady_clock::now();
+  if (!ctx) return fail(nullptr, TEM_EINVAL, "ctx is NULL");
+  if (!ctx->fwd_valid)
+    return fail(ctx, TEM_ESTATE, "tem_jacobian_apply needs a preceding tem_forward with keep_solutions");
+  if (!dm || !ddata) return fail(ctx, TEM_EINVAL, "dm and ddata must not be NULL");
+  const int J = ctx->fwd_J, T = ctx->fwd_T, n_rx = ctx->fwd_nrx, n_src = ctx->fwd_nsrc;
+  if (n_rx < 1) return fail(ctx, TEM_EINVAL, "the forward had no receivers");
+  const long long ncell = (long long)ctx->nx * ctx->ny * ctx->nz;
+  for (long long i = 0; i < ncell; ++i)
+    if (!std::isfinite(dm[i])) return fail(ctx, TEM_EINVAL, "non-finite dm");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  int rc;
+  if ((rc = order_after_caller(ctx))) return rc;
+  hipStream_t st = ctx->work;
+  // the sensitivity systems are FP64, to the FP64 default after a precision-1 forward
+  tem_solve_opts o = ctx->fwd_opts;
+  if (o.precision == 1) o.rtol = 1e-12;
+  const size_t vb = (size_t)J * ctx->n3 * sizeof(double2);
+  DevBuf H, Mu, Rr, Pb, Q, ddm;
+  auto cleanup = [&]() {
+    for (DevBuf* b : {&H, &Mu, &Rr, &Pb, &Q, &ddm}) release(*b);
+  };
+  if ((rc = ensure(ctx, H, vb)) || (rc = ensure(ctx, Mu, vb)) || (rc = ensure(ctx, Rr, vb)) ||
+      (rc = ensure(ctx, Pb, 2 * vb)) || (rc = ensure(ctx, Q, vb)) || (rc = ensure(ctx, ddm, ncell * sizeof(double)))) {
+    cleanup();
+    return rc;
+  }
+  const double* shd = (const double*)ctx->sh.p;
+  std::unique_ptr<tem::CocgState> hs(new tem::CocgState());
+  tem_stats S{};
+  S.n_shifts = J;
+  S.converged = 1;
+  hipError_t e = hipMemcpyAsync(ddm.p, dm, ncell * sizeof(double), hipMemcpyHostToDevice, st);
+  for (int s = 0; s < n_src && e == hipSuccess; ++s) {
+    // h_j = -s_j (dM/M) y_j, then (A + s_j) dy_j = h_j by batched COCG (a
+    // different right-hand side per shift), then the receivers of
+    // Re sum_j c_jk dx_j, as in the forward
+    tem::launch_jvp_rhs(ctx->g, J, ctx->d_sigma, (const double*)ddm.p, ctx->d_mass, shd, shd + TEM_MAX_SHIFTS,
+                        (const double2*)ctx->Y[s].p, (double2*)H.p, st);
+    e = hipGetLastError();
+    if (e != hipSuccess) break;
+    double2* P0 = (double2*)Pb.p;
+    double2* P1 = P0 + (size_t)J * ctx->n3;
+    int its = 0;
+    const int r3 = cocg_solve(ctx, J, (const double2*)H.p, (double2*)Mu.p, (double2*)Rr.p, P0, P1, (double2*)Q.p,
+                              o.rtol, o.max_iter, *hs, its);
+    if (r3 == TEM_ENOCONV) {
+      S.converged = 0;
+    } else if (r3 != TEM_OK) {
+      cleanup();
+      return r3;
+    }
+    S.iterations = its;
+    for (int j = 0; j < J; ++j) {
+      S.iters_per_shift[j] = hs->iters[j];
+      S.est_res[j] = hs->hn2[j] > 0 ? std::sqrt(hs->rn2[j] / hs->hn2[j]) : 0.0;
+      S.unknown_updates += (double)ctx->nunk * hs->iters[j];
+    }
+    tem::launch_receivers(ctx->g, (const double2*)Mu.p, J, ctx->d_dinv, (const double*)ctx->C.p, T,
+                          (const int*)ctx->rx.p, n_rx, ctx->ks, (double*)ctx->data.p, st);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(ddata + (size_t)s * T * n_rx, ctx->data.p, (size_t)T * n_rx * sizeof(double),
+                         hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  cleanup();
+  if (e != hipSuccess) return fail(ctx, TEM_EHIP, std::string("jacobian: ") + hipGetErrorString(e));
+  S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  if (stats) *stats = S;
+  return S.converged ? TEM_OK : fail(ctx, TEM_ENOCONV, "sensitivity COCG did not reach rtol within max_iter");
+}
+
+int tem_engine_create(tem_engine** out, int device, int max_jobs) {
+  if (!out) return fail(nullptr, TEM_EINVAL, "engine pointer is NULL");
+  *out = nullptr;
+  if (max_jobs <= 0) max_jobs = tem::kMaxBatchJobs;
+  if (max_jobs > tem::kMaxBatchJobs) return fail(nullptr, TEM_EINVAL, "max_jobs must be at most 16");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(nullptr, TEM_EHIP, "no such HIP device");
+  if (hipSetDevice(device) != hipSuccess) return fail(nullptr, TEM_EHIP, "hipSetDevice failed");
+  std::unique_ptr<tem_engine> E(new tem_engine());
+  E->device = device;
+  E->max_jobs = max_jobs;
+  auto chk = [&](hipError_t e, const char* what) -> int {
+    if (e == hipSuccess) return TEM_OK;
+    return fail(nullptr, TEM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  };
+  const size_t tab = (size_t)tem_engine::kGens * tem::kMaxBatchJobs * sizeof(tem::BatchJob);
+  int rc;
+  if ((rc = chk(hipStreamCreateWithFlags(&E->stream, hipStreamNonBlocking), "engine stream")) ||
+      (rc = chk(hipMalloc(&E->d_tables, tab), "engine tables")) ||
+      (rc = chk(hipHostMalloc((void**)&E->h_tables, tab, hipHostMallocDefault), "engine tables")) ||
+      (rc = chk(hipMalloc(&E->d_heads, tem::kMaxBatchJobs * sizeof(tem::SolveHead)), "engine heads")) ||
+      (rc = chk(hipHostMalloc((void**)&E->h_heads, 2 * tem::kMaxBatchJobs * sizeof(tem::SolveHead),
+                              hipHostMallocDefault), "engine heads")) ||
+      (rc = chk(hipEventCreateWithFlags(&E->head_ev[0], hipEventDisableTiming), "engine events")) ||
+      (rc = chk(hipEventCreateWithFlags(&E->head_ev[1], hipEventDisableTiming), "engine events"))) {
+    tem_engine_destroy(E.release());
+    return rc;
+  }
+  E->worker = std::thread(engine_worker, E.get());
+  *out = E.release();
+  return TEM_OK;
+}
+
+int tem_attach_engine(tem_ctx* ctx, tem_engine* eng) {
+  if (!ctx) return fail(nullptr, TEM_EINVAL, "ctx is NULL");
+  if (eng) {
+    if (eng->device != ctx->device) return fail(ctx, TEM_EINVAL, "engine and context are on different devices");
+    int ntx = 0, nty = 0;
+    if (tem::batch_tiles(ctx->g, &ntx, &nty) > tem::kReduceSlots)
+      return fail(ctx, TEM_EINVAL, "grid too large for batched launches: more tiles than partial-sum slots");
+  }
+  ctx->engine = eng;
+  return TEM_OK;
+}
+
+int tem_engine_stats(tem_engine* eng, long long* blocks, long long* job_blocks, int* max_jobs, int* max_contexts) {
+  if (!eng) return fail(nullptr, TEM_EINVAL, "engine is NULL");
+  std::lock_guard<std::mutex> lk(eng->mu);
+  if (blocks) *blocks = eng->blocks;
+  if (job_blocks) *job_blocks = eng->job_blocks;
+  if (max_jobs) *max_jobs = eng->max_jobs_seen;
+  if (max_contexts) *max_contexts = eng->max_ctx_seen;
+  return TEM_OK;
+}
+
+void tem_engine_destroy(tem_engine* eng) {
+  if (!eng) return;
+  (void)hipSetDevice(eng->device);
+  if (eng->worker.joinable()) {
+    {
+      std::lock_guard<std::mutex> lk(eng->mu);
+      eng->stop = true;
+    }
+    eng->cv.notify_all();
+    eng->worker.join();
+  }
+  if (eng->stream) (void)hipStreamSynchronize(eng->stream);
+  for (hipEvent_t e : eng->head_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (eng->d_tables) (void)hipFree(eng->d_tables);
+  if (eng->h_tables) (void)hipHostFree(eng->h_tables);
+  if (eng->d_heads) (void)hipFree(eng->d_heads);
+  if (eng->h_heads) (void)hipHostFree(eng->h_heads);
+  if (eng->stream) (void)hipStreamDestroy(eng->stream);
+  delete eng;
 }
 
 int tem_sizes(const tem_ctx* ctx, long long* n_storage, long long* n_unknowns) {

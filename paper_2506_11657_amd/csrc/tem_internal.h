@@ -87,6 +87,27 @@ struct CocgState {
   int J;                                           // set by the host
 };
 
+// One multi-shift solve in the batched launches of a solve engine: its grid,
+// operator and workspace, and where its blocks sit in the batched grids.  The
+// seed stencil of every job uses the (64, 8, 1) tile.
+struct BatchJob {
+  GridArgs g;
+  const double* dinv;
+  double s0;
+  double* R;          // residual ring: B slots of 3 nn
+  double* pbuf;       // seed direction, two slots (ping-pong by iteration parity)
+  double* q;
+  double* part_st;    // stencil partial sums, one per tile
+  double* part_up;    // update partial sums
+  SolveState* st;
+  double2* Y;         // per-shift iterates y_j, J x 3 nn
+  double2* P;         // per-shift directions p_j, J x 3 nn
+  int J;
+  int tile0, ntx, nty, ntiles;  // stencil: first block of this job and its tiles (x, y, total)
+  int bu0, nbu;                 // block update: first block and block count
+};
+constexpr int kMaxBatchJobs = 16;
+
 struct Reduce {
   double* partials;      // kReduceSlots * kMaxShifts
   unsigned int* counter; // completion counters (zero between kernels)
@@ -112,7 +133,7 @@ void launch_scale(long long n, const double* a, const double* x, double* y, hipS
 void launch_to_complex(long long n, const double* x, double2* y, hipStream_t s);
 void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, double2* Y, double2* P,
                       int J, Reduce red, SolveState* st, hipStream_t s);
-void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, float2* Y, float2* P,
+void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, double2* Y, float2* P,
                       int J, Reduce red, SolveState* st, hipStream_t s);
 // with t0 != nullptr the dispatch records its own start (t0) and stop (t1) events
 void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold, double* pnew, double* q,
@@ -122,7 +143,8 @@ void launch_seed_update(const GridArgs& g, const double* r, const double* q, dou
                         SolveState* st, int local, Sink& k, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_block_update(const GridArgs& g, const double* R, double2* Y, double2* P, int J, int B,
                          const SolveState* st, Sink& k);
-void launch_block_update(const GridArgs& g, const double* R, float2* Y, float2* P, int J, int B,
+// precision 1: y_j in FP64, p_j in FP32
+void launch_block_update(const GridArgs& g, const double* R, double2* Y, float2* P, int J, int B,
                          const SolveState* st, Sink& k);
 // J node-padded complex vectors, FP32 storage widened to FP64: sign 0 sets
 // Y_j = X_j for all j; sign +1 / -1 adds / subtracts X_j for the j in mask
@@ -141,11 +163,27 @@ void launch_gather_solutions(const GridArgs& g, const double2* Y, int J, const d
                              hipStream_t s);
 void launch_scatter_storage(const GridArgs& g, const double2* xpub, const double* w, double2* xpad, hipStream_t s);
 void launch_gather_storage(const GridArgs& g, const double2* xpad, const double* w, double2* xpub, hipStream_t s);
+// two-pass form: receiver values and channel contraction straight from the seed residual ring
+void launch_ring_receivers(const GridArgs& g, const double* R, int B, const double* dinv, const int* rx, int n_rx,
+                           int ks, double* hq, int init, Sink& k);
+void launch_ring_contract_init(const GridArgs& g, const double* r0, const double* W, int T, double* U, hipStream_t s);
+void launch_ring_contract(const GridArgs& g, const double* R, int B, const double* W, int T, double* U,
+                          const SolveState* st, Sink& k);
+void launch_ring_fields(const GridArgs& g, const double* U, int T, const double* dinv, double* fields,
+                        const int* rx, int n_rx, int ks, double* d, hipStream_t s);
 long long storage_edges(const GridArgs& g);
 int cstencil_partials(const GridArgs& g);
 int seed_stencil_blocks(const GridArgs& g);
 // seed stencil tile shape for a grid on a device with n_cu compute units
 int choose_seed_tile(const GridArgs& g, int n_cu);
+// batched launches of a solve engine: every job's blocks in one grid per kernel
+int batch_tiles(const GridArgs& g, int* ntx, int* nty);  // (64, 8, 1) tiles of a grid
+int block_update_blocks(const GridArgs& g);
+void launch_seed_stencil_batch(const BatchJob* jobs, int njobs, int total_tiles, int B, int local, Sink& k);
+void launch_seed_update_batch(const BatchJob* jobs, int njobs, int B, int local, Sink& k);
+void launch_shift_block_batch(const BatchJob* jobs, int njobs, int max_J, Sink& k);
+void launch_block_update_batch(const BatchJob* jobs, int njobs, int total_blocks, int B, Sink& k);
+void launch_gather_heads(const BatchJob* jobs, int njobs, SolveHead* out, Sink& k);
 // adjoint: batched COCG (state is an opaque device struct of cocg_state_bytes())
 size_t cocg_state_bytes();
 int cocg_partials(const GridArgs& g, int J);
@@ -169,6 +207,9 @@ void launch_cocg_update(const GridArgs& g, int J, float2* Mu, float2* Rr, const 
 void launch_grad_edges(const GridArgs& g, int J, const double2* Mu, const double2* Y, const double* dinv,
                        const double* sre, const double* sim, double* z, hipStream_t s);
 void launch_grad_cells(const GridArgs& g, const double* sigma, const double* z, double* grad, hipStream_t s);
+// Jacobian action: h_j = -s_j (dM/M) y_j with dM the edge mass of dm_c sigma_c (per cell)
+void launch_jvp_rhs(const GridArgs& g, int J, const double* sigma, const double* dm, const double* mass,
+                    const double* sre, const double* sim, const double2* Y, double2* H, hipStream_t s);
 void launch_caxpy_shifts(const GridArgs& g, int J, const double* gamma, const double2* Yr, double2* Mu,
                          hipStream_t s);
 // per shift (w_j, rho_j) (Hermitian, re and im) and (w_j, w_j): partial sums at

@@ -311,7 +311,7 @@ __device__ void stencil_tile(const GridArgs& g, const double* __restrict__ dinv,
 // fluxes of KZ + 1 planes are formed in LDS from the 1-D width products, and
 // emit(v, c, (K p')_c, u, M^-1/2) receives every owned edge.
 template <int TX, int TY, int KZ, typename FetchFn, typename PreFn, typename CombineFn, typename EmitFn>
-__device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ dinv, int zb, FetchFn fetch, PreFn pre,
+__device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ dinv, int bx, int by, int zb, FetchFn fetch, PreFn pre,
                                 CombineFn combine, EmitFn emit) {
   constexpr int NP = KZ + 2;                                // planes loaded
   constexpr int NE = (TX + 2) * (TY + 2);                   // entries per plane
@@ -327,7 +327,7 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
   __shared__ double wzh[KZ + 1], wzi[KZ + 1], wzd[KZ + 1];
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = tx + TX * ty;
-  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+  const int i0 = bx * TX, j0 = by * TY;
   const int k0 = zb * KZ;
   const int i = i0 + tx, j = j0 + ty;
   const bool own = (i < g.nx) && (j < g.ny);
@@ -482,19 +482,18 @@ __device__ inline double from_lane(double v, int l) {
 // block and the next kernel sums them in a fixed order, so results are
 // bitwise repeatable and no device-scope fences are needed.
 // ---------------------------------------------------------------------------
-// 4 waves per SIMD keeps two 512-thread tiles resident per CU (the LDS of
-// two tiles fits); the staged registers must then fit in 128 VGPRs
+// One tile of the seed stencil: tile (bx, by, bz) of the grid, block index bid
+// among the stencil's nst blocks (its partial-sum slot).
 template <int TX, int TY, int KZ, bool B3D>
-__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(TX * TY * KZ > 512 ? 2 : 4))) k_seed_stencil(GridArgs g, const double* __restrict__ r,
-                                                          const double* __restrict__ pold,
-                                                          double* __restrict__ pnew, double* __restrict__ q,
-                                                          const double* __restrict__ dinv, double s0,
-                                                          const double* __restrict__ upd_partials,
-                                                          double* __restrict__ partials, SolveState* st, int local) {
+__device__ __forceinline__ void seed_stencil_tile(const GridArgs& g, const double* __restrict__ r,
+                                                  const double* __restrict__ pold, double* __restrict__ pnew,
+                                                  double* __restrict__ q, const double* __restrict__ dinv, double s0,
+                                                  const double* __restrict__ upd_partials,
+                                                  double* __restrict__ partials, SolveState* st, int local, int bx,
+                                                  int by, int bz, int bid) {
   constexpr int NT = TX * TY;
   constexpr int NPART = (UPD_BLOCKS + NT - 1) / NT;
   __shared__ double red[(NT + kWave - 1) / kWave];
-  const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   const int tid = threadIdx.x + TX * threadIdx.y;
   // requested before the stencil's own loads so that their round trips
   // overlap those loads: the update's partials, rr_{k-1} and the block length
@@ -540,20 +539,36 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(TX 
     auto fetch = [&](long long v, int c) { return RP{r[c * g.nn + v], pold[c * g.nn + v]}; };
     auto combine = [&](const RP& x) { return x.r + beta * x.p; };
     auto emit_raw = [&](long long v, int c, double kp, const RP& x, double d) { emit(v, c, kp, combine(x), d); };
-    stencil_block3d<TX, TY, KZ>(g, dinv, blockIdx.z, fetch, pre, combine, emit_raw);
+    stencil_block3d<TX, TY, KZ>(g, dinv, bx, by, bz, fetch, pre, combine, emit_raw);
   } else {
     pre();
     auto load = [&](long long v, int c) { return r[c * g.nn + v] + beta * pold[c * g.nn + v]; };
-    stencil_tile<double, TX, TY, KZ>(g, dinv, blockIdx.z, load, emit);
+    stencil_tile<double, TX, TY, KZ>(g, dinv, bz, load, emit);
   }
   const double s = block_sum_n<NT>(dot, red, tid);
   if (tid == 0) partials[bid] = s;
 }
 
-__global__ void __launch_bounds__(UPD_T) k_seed_update(long long n, const double* __restrict__ r,
-                                                       const double* __restrict__ q, double* __restrict__ rnext,
-                                                       const double* __restrict__ st_partials, int n_st,
-                                                       double* __restrict__ partials, SolveState* st, int local) {
+// 4 waves per SIMD keeps two 512-thread tiles resident per CU (the LDS of
+// two tiles fits); the staged registers must then fit in 128 VGPRs
+template <int TX, int TY, int KZ, bool B3D>
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(TX * TY * KZ > 512 ? 2 : 4))) k_seed_stencil(GridArgs g, const double* __restrict__ r,
+                                                          const double* __restrict__ pold,
+                                                          double* __restrict__ pnew, double* __restrict__ q,
+                                                          const double* __restrict__ dinv, double s0,
+                                                          const double* __restrict__ upd_partials,
+                                                          double* __restrict__ partials, SolveState* st, int local) {
+  const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  seed_stencil_tile<TX, TY, KZ, B3D>(g, r, pold, pnew, q, dinv, s0, upd_partials, partials, st, local, blockIdx.x,
+                                     blockIdx.y, blockIdx.z, bid);
+}
+
+// Block blk of the nblk blocks of one seed update (grid-stride over the n entries).
+__device__ __forceinline__ void seed_update_block(long long n, const double* __restrict__ r,
+                                                  const double* __restrict__ q, double* __restrict__ rnext,
+                                                  const double* __restrict__ st_partials, int n_st,
+                                                  double* __restrict__ partials, SolveState* st, int local, int blk,
+                                                  int nblk) {
   __shared__ double red[UPD_T / 64];
   const int tid = threadIdx.x;
   // requested first, so that their round trips overlap the loads of r and q
@@ -564,8 +579,8 @@ __global__ void __launch_bounds__(UPD_T) k_seed_update(long long n, const double
   const int B = st->B;
   // the first UPD_PF grid-stride elements are loaded before the reduction so
   // that their latency overlaps the sum of the stencil's partials
-  const long long stride = (long long)gridDim.x * UPD_T;
-  const long long e0 = blockIdx.x * (long long)UPD_T + tid;
+  const long long stride = (long long)nblk * UPD_T;
+  const long long e0 = blk * (long long)UPD_T + tid;
   double rv[UPD_PF], qv[UPD_PF];
 #pragma unroll
   for (int m = 0; m < UPD_PF; ++m) {
@@ -578,7 +593,7 @@ __global__ void __launch_bounds__(UPD_T) k_seed_update(long long n, const double
   for (int i = tid + UPD_T; i < n_st; i += UPD_T) sp += st_partials[i];
   const double pap = block_total_n<UPD_T>(sp, red, tid);
   const double alpha = (pap > 0.0 && isfinite(pap)) ? rr / pap : 0.0;
-  if (blockIdx.x == 0 && tid == 0) {
+  if (blk == 0 && tid == 0) {
     if (!(pap > 0.0 && isfinite(pap))) st->breakdown = 1;
     if (local == 0) {  // alpha, beta of the step before this block, for the shift recurrences
       st->carry_alpha = st->alpha_h[B - 1];
@@ -603,7 +618,14 @@ __global__ void __launch_bounds__(UPD_T) k_seed_update(long long n, const double
     acc += v * v;
   }
   const double s = block_sum_n<UPD_T>(acc, red, tid);
-  if (tid == 0) partials[blockIdx.x] = s;
+  if (tid == 0) partials[blk] = s;
+}
+
+__global__ void __launch_bounds__(UPD_T) k_seed_update(long long n, const double* __restrict__ r,
+                                                       const double* __restrict__ q, double* __restrict__ rnext,
+                                                       const double* __restrict__ st_partials, int n_st,
+                                                       double* __restrict__ partials, SolveState* st, int local) {
+  seed_update_block(n, r, q, rnext, st_partials, n_st, partials, st, local, blockIdx.x, gridDim.x);
 }
 
 // Per-shift recurrences for one block of B seed steps, replayed from the
@@ -614,8 +636,8 @@ __global__ void __launch_bounds__(UPD_T) k_seed_update(long long n, const double
 //   alpha^s_k = a_k zeta_{k+1}/zeta_k,  beta^s_k = b_k (zeta_{k+1}/zeta_k)^2,
 //   y_{k+1} = y_k + alpha^s_k p_k,  p_{k+1} = zeta_{k+1} r_{k+1} + beta^s_k p_k,
 // accumulated as coefficients of the block's starting p and residuals r_l.
-__global__ void __launch_bounds__(64) k_shift_block(const double* __restrict__ upd_partials, SolveState* st) {
-  const int j = blockIdx.x, lane = threadIdx.x;
+__device__ __forceinline__ void shift_block_wave(const double* __restrict__ upd_partials, SolveState* st, int j) {
+  const int lane = threadIdx.x;
   constexpr int NPART = (UPD_BLOCKS + kWave - 1) / kWave;
   __shared__ double red[1];
   // the update's partials and the state's scalars are all requested before
@@ -713,19 +735,26 @@ __global__ void __launch_bounds__(64) k_shift_block(const double* __restrict__ u
   }
 }
 
+__global__ void __launch_bounds__(64) k_shift_block(const double* __restrict__ upd_partials, SolveState* st) {
+  shift_block_wave(upd_partials, st, blockIdx.x);
+}
+
 // Deferred shift update after a block of BB seed iterations:
 //   p_j <- a_j p_j + sum_l e_jl r_l,   y_j <- y_j + c_j p_j + sum_l d_jl r_l
 // for every shift updated in the block (coefficients from k_shift_block).
+// y_j is stored in YV and p_j in PV: double2 both for the FP64 path, double2
+// and float2 for precision 1 (the iterate accumulates in FP64, only the
+// search direction is rounded to FP32 once per block).
 // The coefficients are the same for every thread, so they are read with
 // uniform loads from the state (scalar registers as FMA operands) rather than
 // staged through LDS, whose broadcast reads stalled the waves; the kernel
 // writes nothing the coefficients could alias.
 constexpr int BU_T = 256;
-template <int BB, typename V>
-__global__ void __launch_bounds__(BU_T) k_block_update(long long n3, const double* __restrict__ R, V* __restrict__ Y,
-                                                       V* __restrict__ P, int J,
-                                                       const SolveState* __restrict__ st) {
-  for (long long e = blockIdx.x * (long long)BU_T + threadIdx.x; e < n3; e += (long long)gridDim.x * BU_T) {
+template <int BB, typename YV, typename PV>
+__device__ __forceinline__ void block_update_block(long long n3, const double* __restrict__ R, YV* __restrict__ Y,
+                                                  PV* __restrict__ P, int J, const SolveState* __restrict__ st,
+                                                  int blk, int nblk) {
+  for (long long e = blk * (long long)BU_T + threadIdx.x; e < n3; e += (long long)nblk * BU_T) {
     double rl[BB];
 #pragma unroll
     for (int l = 0; l < BB; ++l) rl[l] = R[(long long)l * n3 + e];
@@ -752,9 +781,68 @@ __global__ void __launch_bounds__(BU_T) k_block_update(long long n3, const doubl
   }
 }
 
-template <typename V>
+template <int BB, typename YV, typename PV>
+__global__ void __launch_bounds__(BU_T) k_block_update(long long n3, const double* __restrict__ R, YV* __restrict__ Y,
+                                                       PV* __restrict__ P, int J,
+                                                       const SolveState* __restrict__ st) {
+  block_update_block<BB, YV, PV>(n3, R, Y, P, J, st, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches: the same per-tile / per-block work as the kernels above for
+// several independent multi-shift solves (jobs) at once, one grid per kernel,
+// each block finding its job in a device table.  A job's tile decomposition,
+// reductions and their order are those of the job run alone in the same
+// batched form, so its results do not depend on the other jobs.
+// ---------------------------------------------------------------------------
+constexpr int kBTX = 64, kBTY = 8, kBKZ = 1;
+
+__global__ void __launch_bounds__(kBTX* kBTY) __attribute__((amdgpu_waves_per_eu(4)))
+k_seed_stencil_batch(const BatchJob* __restrict__ jobs, int njobs, int B, int local) {
+  int j = 0;
+  while (j + 1 < njobs && (int)blockIdx.x >= jobs[j + 1].tile0) ++j;
+  const BatchJob& jb = jobs[j];
+  const long long n3 = 3 * jb.g.nn;
+  const int t = (int)blockIdx.x - jb.tile0;
+  const int bx = t % jb.ntx, by = (t / jb.ntx) % jb.nty, bz = t / (jb.ntx * jb.nty);
+  seed_stencil_tile<kBTX, kBTY, kBKZ, true>(jb.g, jb.R + (long long)local * n3, jb.pbuf + ((local + 1) & 1) * n3,
+                                            jb.pbuf + (local & 1) * n3, jb.q, jb.dinv, jb.s0, jb.part_up, jb.part_st,
+                                            jb.st, local, bx, by, bz, t);
+}
+
+__global__ void __launch_bounds__(UPD_T) k_seed_update_batch(const BatchJob* __restrict__ jobs, int B, int local) {
+  const BatchJob& jb = jobs[blockIdx.x / UPD_BLOCKS];
+  const long long n3 = 3 * jb.g.nn;
+  seed_update_block(n3, jb.R + (long long)local * n3, jb.q, jb.R + (long long)((local + 1) % B) * n3, jb.part_st,
+                    jb.ntiles, jb.part_up, jb.st, local, blockIdx.x % UPD_BLOCKS, UPD_BLOCKS);
+}
+
+__global__ void __launch_bounds__(64) k_shift_block_batch(const BatchJob* __restrict__ jobs) {
+  const BatchJob& jb = jobs[blockIdx.y];
+  if ((int)blockIdx.x >= jb.J) return;
+  shift_block_wave(jb.part_up, jb.st, blockIdx.x);
+}
+
+template <int BB>
+__global__ void __launch_bounds__(BU_T) k_block_update_batch(const BatchJob* __restrict__ jobs, int njobs) {
+  int j = 0;
+  while (j + 1 < njobs && (int)blockIdx.x >= jobs[j + 1].bu0) ++j;
+  const BatchJob& jb = jobs[j];
+  block_update_block<BB, double2, double2>(3 * jb.g.nn, jb.R, jb.Y, jb.P, jb.J, jb.st, (int)blockIdx.x - jb.bu0,
+                                           jb.nbu);
+}
+
+// the leading SolveHead of every job's state, contiguous, for one copy to the host
+__global__ void k_gather_heads(const BatchJob* __restrict__ jobs, int njobs, SolveHead* out) {
+  if ((int)blockIdx.x >= njobs) return;
+  const int* src = (const int*)jobs[blockIdx.x].st;
+  int* dst = (int*)(out + blockIdx.x);
+  for (int i = threadIdx.x; i < (int)(sizeof(SolveHead) / sizeof(int)); i += blockDim.x) dst[i] = src[i];
+}
+
+template <typename YV, typename PV>
 __global__ void __launch_bounds__(UPD_T) k_seed_init(long long n3, const double* __restrict__ gv, double* r0,
-                                                     double* pold, V* Y, V* P, int J,
+                                                     double* pold, YV* Y, PV* P, int J,
                                                      double* __restrict__ partials, SolveState* st) {
   __shared__ double red[UPD_T / 64];
   double acc = 0.0;
@@ -948,6 +1036,113 @@ __global__ void k_receivers(GridArgs g, const double2* __restrict__ Y, int J, co
     const double* cc = C + 2 * ((long long)jj * T + ch);
     acc += cc[0] * zr - cc[1] * zi;
   }
+  d[(long long)ch * n_rx + r] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Two-pass form (no per-shift vectors).  Every shifted iterate is a fixed
+// combination of the seed residuals, y_j = sum_k gamma_jk r_k, and so is every
+// channel, u(t) = sum_k r_k w_kt with w_kt = Re sum_j c_jt gamma_jk (the host
+// derives gamma from the seed's recorded alpha_k, beta_k).  The kernels below
+// read the residuals a block leaves in its ring: after the block whose first
+// iteration is k0, slot l holds r_{k0+l} for l = 1 .. B-1 and slot 0 holds
+// r_{k0+B}; r_0 = g sits in slot 0 before the first block.
+// ---------------------------------------------------------------------------
+
+// q_r . (M^-1/2 r_k) for the block's residuals (init: r_0 only), into
+// hq[(l - 1) * n_rx + r] (init: hq[r]); receiver rows as in k_receivers.
+__global__ void k_ring_receivers(GridArgs g, const double* __restrict__ R, int B, const double* __restrict__ dinv,
+                                 const int* __restrict__ rx, int n_rx, int ks, double* hq, int init) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nl = init ? 1 : B;
+  if (idx >= nl * n_rx) return;
+  const int l = init ? 0 : idx / n_rx + 1;
+  const int r = idx % n_rx;
+  const double* rv = R + (long long)(l % B) * 3 * g.nn;
+  const int i = rx[2 * r], j = rx[2 * r + 1];
+  const double hx = g.h[0][i], hy = g.h[1][j];
+  const double inva = -1.0 / (hx * hy);
+  const long long e[4] = {0 * g.nn + node_of(g, i, j, ks), 1 * g.nn + node_of(g, i + 1, j, ks),
+                          0 * g.nn + node_of(g, i, j + 1, ks), 1 * g.nn + node_of(g, i, j, ks)};
+  const double w[4] = {hx * inva, hy * inva, -hx * inva, -hy * inva};
+  double acc = 0.0;
+  for (int m = 0; m < 4; ++m) acc += w[m] * dinv[e[m]] * rv[e[m]];
+  hq[idx] = acc;
+}
+
+// U[t][e] = r_0[e] W[0][t] (padded layout, channel-major): the first term.
+__global__ void k_ring_contract_init(long long n3, const double* __restrict__ r0, const double* __restrict__ W,
+                                     int T, double* U) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= n3) return;
+  const double v = r0[e];
+  for (int t = 0; t < T; ++t) U[(long long)t * n3 + e] = v * W[t];
+}
+
+// U[t][e] += sum_{l=1..B} r_{k0+l}[e] W[k0+l][t] for the block just finished
+// (k0 = st->k - B): an (entries x B) x (B x T) product on FP64 MFMA
+// (v_mfma_f64_16x16x4f64, lane layout as in k_contract), one wave per 16
+// entries and all T <= 64 channels.
+__global__ void __launch_bounds__(256) k_ring_contract(long long n3, const double* __restrict__ R, int B,
+                                                       const double* __restrict__ W, int T, double* U,
+                                                       const SolveState* __restrict__ st) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long e0 = ((long long)blockIdx.x * 4 + wave) * 16;
+  const int row = lane & 15, kq = lane >> 4;
+  const long long ea = e0 + row;
+  const long long k0 = (long long)st->k - B;
+  const int nT = (T + 15) / 16;
+  d4 acc[4];
+  for (int t = 0; t < 4; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int lb = 0; lb < B; lb += 4) {
+    const int l = lb + kq + 1;  // residual r_{k0+l}, l = 1 .. B
+    const double a = (l <= B && ea < n3) ? R[(long long)(l % B) * n3 + ea] : 0.0;
+    for (int t = 0; t < nT; ++t) {
+      const int ch = t * 16 + row;
+      const double b = (l <= B && ch < T) ? W[(k0 + l) * T + ch] : 0.0;
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+    }
+  }
+  for (int t = 0; t < nT; ++t) {
+    const int ch = t * 16 + row;
+    if (ch >= T) continue;
+    for (int r = 0; r < 4; ++r) {
+      const long long e = e0 + 4 * r + kq;
+      if (e < n3) U[(long long)ch * n3 + e] += acc[t][r];
+    }
+  }
+}
+
+// fields[t][e] = dinv_e U[t][node(e)] in storage order, and the receivers
+// d[t][r] = q_r . (M^-1/2 U[t]) (one thread per (channel, receiver) after the
+// fields, in a second launch)
+__global__ void k_ring_fields(GridArgs g, const double* __restrict__ U, int T, const double* __restrict__ dinv,
+                              double* fields, long long nstore) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= nstore) return;
+  long long node;
+  const int c = storage_to_node(g, e, &node);
+  if (c < 0) return;
+  const long long n3 = 3 * g.nn;
+  const double d = dinv[c * g.nn + node];
+  for (int t = 0; t < T; ++t) fields[(long long)t * nstore + e] = d * U[(long long)t * n3 + c * g.nn + node];
+}
+
+__global__ void k_ring_field_receivers(GridArgs g, const double* __restrict__ U, int T,
+                                       const double* __restrict__ dinv, const int* __restrict__ rx, int n_rx,
+                                       int ks, double* d) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= T * n_rx) return;
+  const int ch = idx / n_rx, r = idx % n_rx;
+  const double* u = U + (long long)ch * 3 * g.nn;
+  const int i = rx[2 * r], j = rx[2 * r + 1];
+  const double hx = g.h[0][i], hy = g.h[1][j];
+  const double inva = -1.0 / (hx * hy);
+  const long long e[4] = {0 * g.nn + node_of(g, i, j, ks), 1 * g.nn + node_of(g, i + 1, j, ks),
+                          0 * g.nn + node_of(g, i, j + 1, ks), 1 * g.nn + node_of(g, i, j, ks)};
+  const double w[4] = {hx * inva, hy * inva, -hx * inva, -hy * inva};
+  double acc = 0.0;
+  for (int m = 0; m < 4; ++m) acc += w[m] * dinv[e[m]] * u[e[m]];
   d[(long long)ch * n_rx + r] = acc;
 }
 
@@ -1213,6 +1408,45 @@ __global__ void k_cocg_update(long long n3, int J, V* Mu, V* Rr, const V* __rest
   }
 }
 
+// Jacobian action (Sec. 4): for a change dm of ln sigma per cell,
+//   dM_e = 1/4 sum over the cells around edge e of dm_c sigma_c V_c   (dM/dm . dm),
+//   (K + s_j M) dx_j = -s_j dM x_j,
+// in the scaled variables (x = D y, dx = D dy, D = M^-1/2):
+//   (A + s_j) dy_j = h_j,   h_j[e] = -s_j (dM_e / M_e) y_j[e].
+// One thread per padded entry writes h_j for every shift.
+__global__ void k_jvp_rhs(GridArgs g, int J, const double* __restrict__ sigma, const double* __restrict__ dm,
+                          const double* __restrict__ mass, const double* __restrict__ sre,
+                          const double* __restrict__ sim, const double2* __restrict__ Y, double2* H) {
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v >= g.nn) return;
+  const int i = (int)(v % g.px);
+  const int j = (int)((v / g.px) % g.py);
+  const int k = (int)(v / ((long long)g.px * g.py));
+  auto sv = [&](int ci, int cj, int ck) {
+    const long long c = ((long long)ck * g.ny + cj) * g.nx + ci;
+    return dm[c] * sigma[c] * g.h[0][ci] * g.h[1][cj] * g.h[2][ck];
+  };
+  double d[3] = {0.0, 0.0, 0.0};
+  if (i < g.nx && j > 0 && j < g.ny && k > 0 && k < g.nz)
+    d[0] = 0.25 * (sv(i, j - 1, k - 1) + sv(i, j, k - 1) + sv(i, j - 1, k) + sv(i, j, k));
+  if (j < g.ny && i > 0 && i < g.nx && k > 0 && k < g.nz)
+    d[1] = 0.25 * (sv(i - 1, j, k - 1) + sv(i, j, k - 1) + sv(i - 1, j, k) + sv(i, j, k));
+  if (k < g.nz && i > 0 && i < g.nx && j > 0 && j < g.ny)
+    d[2] = 0.25 * (sv(i - 1, j - 1, k) + sv(i, j - 1, k) + sv(i - 1, j, k) + sv(i, j, k));
+  const long long n3 = 3 * g.nn;
+  for (int c = 0; c < 3; ++c) {
+    const long long e = c * g.nn + v;
+    const double m = mass[e];
+    const double w = m > 0.0 ? d[c] / m : 0.0;
+    for (int q = 0; q < J; ++q) {
+      const double2 y = Y[(long long)q * n3 + e];
+      // -s (w y), s = (sre + i sim)
+      const double wr = w * y.x, wi = w * y.y;
+      H[(long long)q * n3 + e] = make_double2(-(sre[q] * wr - sim[q] * wi), -(sre[q] * wi + sim[q] * wr));
+    }
+  }
+}
+
 // z_e += sum_j Re(s_j mu_j[e] y_j[e]) / M_e  (lambda_j x_j with lambda = D mu, x = D y)
 __global__ void k_grad_edges(long long n3, int J, const double2* __restrict__ Mu, const double2* __restrict__ Y,
                              const double* __restrict__ dinv, const double* sre, const double* sim, double* z) {
@@ -1321,6 +1555,14 @@ long long storage_edges(const GridArgs& g) {
 }
 
 
+int batch_tiles(const GridArgs& g, int* ntx, int* nty) {
+  *ntx = (g.nx + kBTX - 1) / kBTX;
+  *nty = (g.ny + kBTY - 1) / kBTY;
+  return *ntx * *nty * ((g.nz + kBKZ - 1) / kBKZ);
+}
+
+int block_update_blocks(const GridArgs& g) { return grid_1d(3 * g.nn, BU_T, 4096); }
+
 void launch_mass(const GridArgs& g, const double* sigma_cell, double* mass, double* dinv, double* sqrtm,
                  hipStream_t s) {
   hipLaunchKernelGGL(k_mass, dim3((unsigned)((g.nn + 255) / 256)), dim3(256), 0, s, g, sigma_cell, mass, dinv,
@@ -1335,18 +1577,18 @@ void launch_to_complex(long long n, const double* x, double2* y, hipStream_t s) 
   hipLaunchKernelGGL(k_to_complex, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, x, y);
 }
 
-template <typename V>
-static void seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, V* Y, V* P, int J, Reduce red,
-                      SolveState* st, hipStream_t s) {
+template <typename YV, typename PV>
+static void seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, YV* Y, PV* P, int J,
+                      Reduce red, SolveState* st, hipStream_t s) {
   const long long n3 = 3 * g.nn;
-  hipLaunchKernelGGL(k_seed_init<V>, dim3(UPD_BLOCKS), dim3(UPD_T), 0, s, n3, gvec, r0, pold, Y, P, J,
+  hipLaunchKernelGGL((k_seed_init<YV, PV>), dim3(UPD_BLOCKS), dim3(UPD_T), 0, s, n3, gvec, r0, pold, Y, P, J,
                      red.partials + kReduceSlots, st);
 }
 void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, double2* Y, double2* P,
                       int J, Reduce red, SolveState* st, hipStream_t s) {
   seed_init(g, gvec, r0, pold, Y, P, J, red, st, s);
 }
-void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, float2* Y, float2* P,
+void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, double2* Y, float2* P,
                       int J, Reduce red, SolveState* st, hipStream_t s) {
   seed_init(g, gvec, r0, pold, Y, P, J, red, st, s);
 }
@@ -1484,24 +1726,50 @@ void launch_shift_block(const GridArgs& g, int J, Reduce red, SolveState* st, Si
   put(k, k_shift_block, dim3(J), dim3(64), 0u, nullptr, nullptr, (const double*)(red.partials + kReduceSlots), st);
 }
 
+void launch_seed_stencil_batch(const BatchJob* jobs, int njobs, int total_tiles, int B, int local, Sink& k) {
+  put(k, k_seed_stencil_batch, dim3(total_tiles), dim3(kBTX, kBTY), 0u, nullptr, nullptr, jobs, njobs, B, local);
+}
 
-template <typename V>
-static void block_update(const GridArgs& g, const double* R, V* Y, V* P, int J, int B, const SolveState* st,
+void launch_seed_update_batch(const BatchJob* jobs, int njobs, int B, int local, Sink& k) {
+  put(k, k_seed_update_batch, dim3(UPD_BLOCKS * njobs), dim3(UPD_T), 0u, nullptr, nullptr, jobs, B, local);
+}
+
+void launch_shift_block_batch(const BatchJob* jobs, int njobs, int max_J, Sink& k) {
+  put(k, k_shift_block_batch, dim3(max_J, njobs), dim3(64), 0u, nullptr, nullptr, jobs);
+}
+
+void launch_block_update_batch(const BatchJob* jobs, int njobs, int total_blocks, int B, Sink& k) {
+  const dim3 grid(total_blocks), block(BU_T);
+  switch (B) {
+    case 16: put(k, k_block_update_batch<16>, grid, block, 0u, nullptr, nullptr, jobs, njobs); break;
+    case 32: put(k, k_block_update_batch<32>, grid, block, 0u, nullptr, nullptr, jobs, njobs); break;
+    case 64: put(k, k_block_update_batch<64>, grid, block, 0u, nullptr, nullptr, jobs, njobs); break;
+    default: put(k, k_block_update_batch<8>, grid, block, 0u, nullptr, nullptr, jobs, njobs); break;
+  }
+}
+
+void launch_gather_heads(const BatchJob* jobs, int njobs, SolveHead* out, Sink& k) {
+  put(k, k_gather_heads, dim3(njobs), dim3(64), 0u, nullptr, nullptr, jobs, njobs, out);
+}
+
+
+template <typename YV, typename PV>
+static void block_update(const GridArgs& g, const double* R, YV* Y, PV* P, int J, int B, const SolveState* st,
                          Sink& k) {
   const long long n3 = 3 * g.nn;
   const dim3 grid(grid_1d(n3, BU_T, 4096)), block(BU_T);
   switch (B) {
-    case 16: put(k, k_block_update<16, V>, grid, block, 0u, nullptr, nullptr, n3, R, Y, P, J, st); break;
-    case 32: put(k, k_block_update<32, V>, grid, block, 0u, nullptr, nullptr, n3, R, Y, P, J, st); break;
-    case 64: put(k, k_block_update<64, V>, grid, block, 0u, nullptr, nullptr, n3, R, Y, P, J, st); break;
-    default: put(k, k_block_update<8, V>, grid, block, 0u, nullptr, nullptr, n3, R, Y, P, J, st); break;
+    case 16: put(k, k_block_update<16, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, Y, P, J, st); break;
+    case 32: put(k, k_block_update<32, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, Y, P, J, st); break;
+    case 64: put(k, k_block_update<64, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, Y, P, J, st); break;
+    default: put(k, k_block_update<8, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, Y, P, J, st); break;
   }
 }
 void launch_block_update(const GridArgs& g, const double* R, double2* Y, double2* P, int J, int B,
                          const SolveState* st, Sink& k) {
   block_update(g, R, Y, P, J, B, st, k);
 }
-void launch_block_update(const GridArgs& g, const double* R, float2* Y, float2* P, int J, int B,
+void launch_block_update(const GridArgs& g, const double* R, double2* Y, float2* P, int J, int B,
                          const SolveState* st, Sink& k) {
   block_update(g, R, Y, P, J, B, st, k);
 }
@@ -1541,6 +1809,35 @@ void launch_receivers(const GridArgs& g, const double2* Y, int J, const double* 
                       const int* rx, int n_rx, int k_s, double* d, hipStream_t s) {
   const int n = T * n_rx;
   hipLaunchKernelGGL(k_receivers, dim3((n + 127) / 128), dim3(128), 0, s, g, Y, J, dinv, C, T, rx, n_rx, k_s, d);
+}
+
+void launch_ring_receivers(const GridArgs& g, const double* R, int B, const double* dinv, const int* rx, int n_rx,
+                           int ks, double* hq, int init, Sink& k) {
+  const int n = (init ? 1 : B) * n_rx;
+  put(k, k_ring_receivers, dim3((unsigned)((n + 255) / 256)), dim3(256), 0u, nullptr, nullptr, g, R, B, dinv, rx,
+      n_rx, ks, hq, init);
+}
+
+void launch_ring_contract_init(const GridArgs& g, const double* r0, const double* W, int T, double* U, hipStream_t s) {
+  const long long n3 = 3 * g.nn;
+  hipLaunchKernelGGL(k_ring_contract_init, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, n3, r0, W, T, U);
+}
+
+void launch_ring_contract(const GridArgs& g, const double* R, int B, const double* W, int T, double* U,
+                          const SolveState* st, Sink& k) {
+  const long long n3 = 3 * g.nn;
+  const unsigned blocks = (unsigned)((n3 + 63) / 64);
+  put(k, k_ring_contract, dim3(blocks), dim3(256), 0u, nullptr, nullptr, n3, R, B, W, T, U, st);
+}
+
+void launch_ring_fields(const GridArgs& g, const double* U, int T, const double* dinv, double* fields,
+                        const int* rx, int n_rx, int ks, double* d, hipStream_t s) {
+  const long long ns = storage_edges(g);
+  if (fields)
+    hipLaunchKernelGGL(k_ring_fields, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, s, g, U, T, dinv, fields, ns);
+  if (n_rx > 0)
+    hipLaunchKernelGGL(k_ring_field_receivers, dim3((unsigned)((T * n_rx + 255) / 256)), dim3(256), 0, s, g, U, T,
+                       dinv, rx, n_rx, ks, d);
 }
 
 void launch_gather_solutions(const GridArgs& g, const double2* Y, int J, const double* dinv, double2* out,
@@ -1649,6 +1946,12 @@ int dot_shifts_blocks(const GridArgs& g) { return grid_1d(3 * g.nn, 256, 128); }
 void launch_dot_shifts(const GridArgs& g, int J, const double2* W, const double2* Rh, double* partials, hipStream_t s) {
   const long long n3 = 3 * g.nn;
   hipLaunchKernelGGL(k_dot_shifts, dim3(dot_shifts_blocks(g), J), dim3(256), 0, s, n3, W, Rh, partials);
+}
+
+void launch_jvp_rhs(const GridArgs& g, int J, const double* sigma, const double* dm, const double* mass,
+                    const double* sre, const double* sim, const double2* Y, double2* H, hipStream_t s) {
+  hipLaunchKernelGGL(k_jvp_rhs, dim3((unsigned)((g.nn + 255) / 256)), dim3(256), 0, s, g, J, sigma, dm, mass, sre, sim,
+                     Y, H);
 }
 
 void launch_grad_cells(const GridArgs& g, const double* sigma, const double* z, double* grad, hipStream_t s) {

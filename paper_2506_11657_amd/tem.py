@@ -22,7 +22,9 @@ STATUS_NAMES = {0: "TEM_OK", -1: "TEM_EINVAL", -2: "TEM_ENOMEM", -3: "TEM_ENOCON
                 -4: "TEM_EBREAKDOWN", -5: "TEM_EHIP", -6: "TEM_ESTATE"}
 
 EXPORTS = ["tem_setup_grid", "tem_set_conductivity", "tem_poles", "tem_forward", "tem_adjoint",
-           "tem_solutions", "tem_apply", "tem_sizes", "tem_destroy", "tem_last_error"]
+           "tem_solutions", "tem_apply", "tem_sizes", "tem_destroy", "tem_last_error",
+           "tem_engine_create", "tem_attach_engine", "tem_engine_stats", "tem_engine_destroy",
+           "tem_jacobian_apply"]
 
 
 class tem_loop(C.Structure):
@@ -36,7 +38,7 @@ class tem_receiver(C.Structure):
 class tem_solve_opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("rtol", C.c_double), ("max_iter", C.c_int), ("block", C.c_int),
                 ("seed_shift", C.c_double), ("refine_max", C.c_int), ("keep_solutions", C.c_int),
-                ("profile", C.c_int)]
+                ("profile", C.c_int), ("method", C.c_int)]
 
 
 class tem_stats(C.Structure):
@@ -81,16 +83,23 @@ def lib():
                                   C.c_int, C.c_int, dp, dp, C.POINTER(tem_solve_opts), dp, C.c_void_p,
                                   C.POINTER(tem_stats)]
         L.tem_adjoint.argtypes = [C.c_void_p, dp, dp, C.POINTER(tem_stats)]
+        L.tem_jacobian_apply.argtypes = [C.c_void_p, dp, dp, C.POINTER(tem_stats)]
         L.tem_solutions.argtypes = [C.c_void_p, C.c_int, dp]
         L.tem_apply.argtypes = [C.c_void_p, C.c_double, C.c_double, dp, dp]
         L.tem_sizes.argtypes = [C.c_void_p, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
         L.tem_destroy.argtypes = [C.c_void_p]
         L.tem_destroy.restype = None
+        L.tem_engine_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.c_int]
+        L.tem_attach_engine.argtypes = [C.c_void_p, C.c_void_p]
+        L.tem_engine_stats.argtypes = [C.c_void_p, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong),
+                                       C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.tem_engine_destroy.argtypes = [C.c_void_p]
         L.tem_last_error.argtypes = [C.c_void_p]
         L.tem_last_error.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("tem_destroy", "tem_last_error"):
+            if name not in ("tem_destroy", "tem_last_error", "tem_engine_destroy"):
                 getattr(L, name).restype = C.c_int
+        L.tem_engine_destroy.restype = None
         _lib = L
     return _lib
 
@@ -127,6 +136,33 @@ def poles(t, degree=0, tol=1e-8, w=None, j_max=TEM_MAX_SHIFTS):
     return xi_c, c_c, err
 
 
+class Engine:
+    """tem_engine_create: a solve engine on one device that batches the FP64
+    multi-shift solves of every attached context into shared launches."""
+
+    def __init__(self, device=0, max_jobs=0):
+        h = C.c_void_p()
+        _check(lib().tem_engine_create(C.byref(h), int(device), int(max_jobs)))
+        self._h = h
+
+    def stats(self):
+        b, jb = C.c_longlong(), C.c_longlong()
+        mj, mc = C.c_int(), C.c_int()
+        _check(lib().tem_engine_stats(self._h, C.byref(b), C.byref(jb), C.byref(mj), C.byref(mc)))
+        return {"blocks": b.value, "job_blocks": jb.value, "max_jobs": mj.value, "max_contexts": mc.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tem_engine_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     """A grid on one device: tem_setup_grid / tem_set_conductivity / tem_forward ..."""
 
@@ -149,6 +185,11 @@ class Context:
         ctx = cls(wl.hx, wl.hy, wl.hz, wl.k_s, device, stream)
         ctx.set_conductivity(wl.sigma)
         return ctx
+
+    def attach(self, engine):
+        """tem_attach_engine: route this context's FP64 solves through engine (None detaches)."""
+        _check(lib().tem_attach_engine(self._h, None if engine is None else engine._h), self._h)
+        self._engine = engine   # kept alive while attached
 
     def close(self):
         if getattr(self, "_h", None):
@@ -184,7 +225,7 @@ class Context:
         _check(lib().tem_set_conductivity(self._h, a.ctypes.data_as(C.c_void_p), flags), self._h)
 
     def forward(self, loops, receivers, xi, c, fields=None, rtol=0.0, max_iter=0, block=0, seed_shift=0.0,
-                precision=0, keep_solutions=False, refine_max=0, allow_noconv=False, profile=False):
+                precision=0, keep_solutions=False, refine_max=0, allow_noconv=False, profile=False, method=0):
         """tem_forward.  loops: list of (i0, i1, j0, j1, current) or objects with
         those attributes; receivers: list of (i, j); xi (J complex); c (J x T
         complex).  fields: optional device tensor (n_src, T, n_storage) float64.
@@ -212,13 +253,14 @@ class Context:
                 raise ValueError("fields must be a device tensor of shape (n_src, T, n_storage)")
             fptr = C.c_void_p(fields.data_ptr())
         opts = tem_solve_opts(int(precision), float(rtol), int(max_iter), int(block), float(seed_shift),
-                              int(refine_max), 1 if keep_solutions else 0, 1 if profile else 0)
+                              int(refine_max), 1 if keep_solutions else 0, 1 if profile else 0, int(method))
         st = tem_stats()
         self.generation += 1
         status = lib().tem_forward(self._h, src, len(loops), rx, n_rx, T, J, _dptr(xr), _dptr(cr), C.byref(opts),
                                    _dptr(data), fptr, C.byref(st))
         _check(status, self._h, allow=(TEM_ENOCONV,) if allow_noconv else ())
         self._n_src = len(loops)
+        self._T, self._n_rx = T, n_rx
         out = st.as_dict()
         out["status"] = STATUS_NAMES[status]
         return data[:, :, :n_rx], out
@@ -241,6 +283,20 @@ class Context:
         _check(lib().tem_apply(self._h, float(np.real(shift)), float(np.imag(shift)), _dptr(x.view(np.float64)),
                                _dptr(y.view(np.float64))), self._h)
         return y
+
+    def jacobian_apply(self, dm):
+        """tem_jacobian_apply: first-order change of the last forward's data
+        (n_src, T, n_rx) for a change dm (nz, ny, nx) of ln sigma."""
+        dm = _f64(dm)
+        if dm.shape != self.shape:
+            raise ValueError("dm must have shape %s" % (self.shape,))
+        J = getattr(self, "_J", 0)
+        if J == 0:
+            raise RuntimeError("no forward run on this context")
+        out = np.zeros((self._n_src, self._T, max(self._n_rx, 1)))
+        st = tem_stats()
+        _check(lib().tem_jacobian_apply(self._h, _dptr(dm), _dptr(out), C.byref(st)), self._h)
+        return out[:, :, :self._n_rx], st.as_dict()
 
     def adjoint(self, w):
         """tem_adjoint: gradient (nz, ny, nx) of phi w.r.t. ln sigma given
