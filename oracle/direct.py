@@ -15,8 +15,10 @@ Each x_j is the plain definition: a pivoted LU solve of the shifted matrix,
 by a banded LU after reverse Cuthill-McKee ordering (LAPACK gbsv) or by a
 general sparse LU (SuperLU) as an independent second solver.
 
-Adjoint (Sec. 4): with M(m) = sum_c e^{m_c} M_c, dA_j/dm_c = s_j e^{m_c} M_c,
-so for a misfit phi(d) with w = dphi/dd,
+Jacobian action and adjoint (Sec. 4): with M(m) = sum_c e^{m_c} M_c,
+dA_j/dm_c = s_j e^{m_c} M_c.  The action J dm solves A_j dx_j = -(dA_j dm) x_j
+and contracts the dx_j like the forward; the adjoint (J^T w) of a misfit
+phi(d) with w = dphi/dd is
     dphi/dm_c = -Re sum_j s_j (lambda_j^T  e^{m_c} M_c  x_j),
     lambda_j  = A_j^-T g_j = A_j^-1 g_j   (A_j complex symmetric),
     g_j       = sum_k c_j(t_k) Q^T w_k.
@@ -138,6 +140,20 @@ def misfit_gradient(prob, shifts, C, w, X=None, method="splu"):
     for j, s in enumerate(shifts):
         grad -= (s * (D.T @ (Lam[:, j] * X[:, j]))).real
     return grad
+
+
+def jacobian_apply(prob, shifts, C, dm, X=None, method="splu"):
+    """J dm: the first-order change of the receiver data (T x n_rx, source 0)
+    for a change dm of ln sigma per cell (Sec. 4, eq. (rmjQ) differentiated):
+    A_j dx_j = -(dA_j/dm . dm) x_j = -s_j (dM/d ln sigma . dm) x_j, and
+    dd_k = Q Re sum_j c_jk dx_j."""
+    if X is None:
+        X = solve_shifted(prob, shifts, prob.F[:, 0], method)
+    dM = prob.mass_derivative() @ np.asarray(dm)   # per edge
+    dX = np.zeros_like(X)
+    for j, s in enumerate(shifts):
+        dX[:, j] = -solve_shifted(prob, [s], s * dM * X[:, j], method)[:, 0]
+    return (prob.Q @ contract(dX, C)).T
 
 
 def data_for_model(prob_factory, sigma, shifts, C, method="splu"):

@@ -4,16 +4,23 @@ Requests (a grid, a conductivity model, 1-4 loops, receivers; forward or
 adjoint) arrive over time.  A scheduler admits a request when its device
 footprint fits in the HBM budget and a slot is free; every admitted request
 runs on its own library context in a worker thread (the C calls release the
-GIL).  Within a request the library already solves up to four loop sources
-(or adjoint receiver rows) at once on separate streams, so the graph-replayed
-solver blocks of all admitted requests are in flight on the device together,
-and a request that arrives while others run is admitted as soon as memory
-and a slot free up.
-All requests share one pole/residue set (the channels are the same).
+GIL), and a request that arrives while others run is admitted as soon as
+memory and a slot free up.  All requests share one pole/residue set (the
+channels are the same).
+
+With batched=True (continuous batching) every request's context is attached
+to one solve engine of the library: the multi-shift solves of all admitted
+requests (their loop sources and adjoint receiver rows) advance together in
+batched launches, one seed stencil and one seed update launch per iteration
+for all of them and one shift-block and block-update launch per 64
+iterations for all their poles, replayed as HIP graphs; a request joins the
+batch at the next 64-iteration boundary after it is admitted and leaves it
+when its shifts have converged.  Without it, each request replays its own
+solver graphs on its own streams and the requests overlap on the device.
 
 Each request's arithmetic is independent of the others (its own buffers,
-fixed-order reductions), so its result is bitwise the same alone or in any
-mix.
+fixed-order reductions whose order does not depend on the batch), so its
+result is bitwise the same alone or in any mix.
 """
 from __future__ import annotations
 
@@ -66,6 +73,7 @@ class Request:
     grad: np.ndarray = None
     stats: dict = field(default_factory=dict)
     error: str = None
+    precision: int = 0           # 1: FP32 search directions + FP64 refinement (not batched)
 
     @property
     def latency(self):
@@ -73,8 +81,10 @@ class Request:
 
 
 class Server:
-    def __init__(self, xi, c, device=0, hbm_budget=64 << 30, max_active=4, rtol=0.0, verbose=False):
+    def __init__(self, xi, c, device=0, hbm_budget=64 << 30, max_active=4, rtol=0.0, verbose=False,
+                 batched=False, max_jobs=0):
         self.verbose = verbose
+        self.engine = tem.Engine(device, max_jobs) if batched else None
         self.xi, self.c = np.asarray(xi), np.asarray(c)
         self.device = device
         self.budget = int(hbm_budget)
@@ -90,9 +100,12 @@ class Server:
         ctx = None
         try:
             ctx = tem.Context(wl.hx, wl.hy, wl.hz, wl.k_s, device=self.device)
+            if self.engine is not None:
+                ctx.attach(self.engine)
             ctx.set_conductivity(wl.sigma)
             keep = req.kind == "adjoint"
-            data, st = ctx.forward(wl.loops, wl.receivers, self.xi, self.c, keep_solutions=keep, rtol=self.rtol)
+            data, st = ctx.forward(wl.loops, wl.receivers, self.xi, self.c, keep_solutions=keep,
+                                   rtol=self.rtol if req.precision == 0 else 0.0, precision=req.precision)
             req.data = data
             req.stats["forward"] = {"iterations": st["iterations"], "unknown_updates": st["unknown_updates"]}
             if keep:
@@ -150,6 +163,11 @@ class Server:
             th.join()
         self._threads = []
         return requests
+
+    def close(self):
+        if self.engine is not None:
+            self.engine.close()
+            self.engine = None
 
 
 def summarize(requests, wall):

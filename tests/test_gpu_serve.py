@@ -72,3 +72,65 @@ def test_admission_by_footprint(tem):
     srv2 = Server(-s, C, hbm_budget=1 << 20)
     r = srv2.run(big, realtime=False)[0]
     assert r.error is not None and "ENOMEM" in r.error
+
+
+def _mixed_requests():
+    """Forward and adjoint requests on three grid sizes (8^3, 12^3, 16^3), one
+    with two loops, and one precision-1 forward (which runs its own launches)."""
+    from paper_2506_11657_amd.serve import Request
+    t = W.log_channels(1e-5, 1e-3, 12)
+    reqs = []
+    for i in range(6):
+        n = (8, 12, 16)[i % 3]
+        wl = W.small_case(n, seed=200 + i, t=t)
+        if i == 2:
+            wl.loops = [W.Loop(1, n // 2, 1, n // 2, 1.0), W.Loop(n // 2, n - 1, 2, n - 2, -1.5)]
+        kind = "adjoint" if i % 2 else "forward"
+        r = Request(rid=i, kind=kind, workload=wl, arrival=0.005 * i)
+        if kind == "adjoint":
+            r.d_obs = np.zeros((len(wl.loops), len(t), len(wl.receivers)))
+        if i == 4:
+            r.precision = 1
+        reqs.append(r)
+    return reqs, t
+
+
+def test_batched_engine_alone_equals_mix_bitwise(tem):
+    """Continuous batching: the FP64 solves of every admitted request run in
+    shared batched launches (one stencil and one update launch per iteration
+    for all of them).  Requests of different grid sizes share launches (the
+    engine saw blocks with several requests' jobs), and every result is
+    bitwise the same as the request served alone through the same engine; the
+    batched results also agree with the unbatched path to rounding."""
+    from paper_2506_11657_amd.serve import Server, summarize
+    import time
+    reqs, t = _mixed_requests()
+    fit = rkfit.rkfit(t, 18)
+    s, C = rkfit.shifts_and_coefficients(fit)
+    srv_alone = Server(-s, C, max_active=1, batched=True)
+    alone = srv_alone.run(_mixed_requests()[0], realtime=False)
+    st_alone = srv_alone.engine.stats()
+    srv_alone.close()
+    srv_mix = Server(-s, C, max_active=4, batched=True)
+    t0 = time.perf_counter()
+    mix = srv_mix.run(reqs, realtime=True)
+    summ = summarize(mix, time.perf_counter() - t0)
+    st_mix = srv_mix.engine.stats()
+    srv_mix.close()
+    print("engine alone:", st_alone, "mix:", st_mix, "summary:", summ)
+    errors = [(r.rid, r.error) for r in mix + alone if r.error is not None]
+    assert summ["completed"] == len(reqs) and not errors, errors
+    assert st_alone["max_contexts"] == 1
+    assert st_mix["max_contexts"] >= 2 and st_mix["max_jobs"] >= 2
+    for a, m in zip(alone, mix):
+        assert np.array_equal(a.data, m.data), a.rid
+        if a.kind == "adjoint":
+            assert np.array_equal(a.grad, m.grad), a.rid
+    # the same requests without the engine: equal to rounding (other tiles)
+    plain = Server(-s, C, max_active=4).run(_mixed_requests()[0], realtime=False)
+    for a, p in zip(alone, plain):
+        assert p.error is None
+        scale = np.abs(p.data).max()
+        assert np.abs(a.data - p.data).max() <= 1e-8 * scale, a.rid
+        if a.kind == "adjoint":
+            assert np.abs(a.grad - p.grad).max() <= 1e-7 * np.abs(p.grad).max(), a.rid
