@@ -210,6 +210,22 @@ int tem_solutions(tem_ctx *ctx, int s, double *X);
  * and those of y are zero.  For operator checks. */
 int tem_apply(tem_ctx *ctx, double shift_re, double shift_im, const double *x, double *y);
 
+/* The operator of tem_apply, y = (K + shift M) x, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  It calls no allocating routine.
+ *   x, y   DEVICE pointers to n_storage complex values each (interleaved re, im,
+ *          storage edge order), owned by the caller; they must not alias.
+ *          Boundary entries of x are ignored; those of y are written as zero.
+ * Staging lives in one fixed device array of 64 MiB per GPU (held until the
+ * process ends), which must hold 2 * 3 (nx+1)(ny+1)(nz+1) * 16 + 256 bytes:
+ * larger grids (about 87^3 cells and up) return TEM_EINVAL without launching
+ * anything.  The array is shared by every call on that GPU and keeps the last
+ * call's contents, so calls that overlap on one GPU (other threads, streams or
+ * contexts) race: serialize them.  Work is ordered after the context's stream
+ * and the context's stream is made to wait for it; the call does not
+ * synchronize.  Results equal tem_apply's. */
+int tem_apply_noalloc(tem_ctx *ctx, double shift_re, double shift_im, const double *x, double *y);
+
 /* Solve engine (serving, form 5): a worker thread on `device` that advances
  * the multi-shift solves of every context attached to it together, in
  * batched launches replayed as HIP graphs: per seed iteration one stencil

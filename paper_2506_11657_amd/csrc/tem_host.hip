@@ -10,6 +10,7 @@
 #include <cstring>
 #include <deque>
 #include <functional>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -26,9 +27,36 @@ using tem::SolveState;
 constexpr size_t kHeadStride = 2048;
 static_assert(sizeof(tem::SolveHead) <= kHeadStride, "pinned head buffer");
 
+// Device memory of tem_apply_noalloc: a fixed array in the code object, one
+// copy per GPU the library is loaded on, held until the process ends.  Its
+// host-side name is only a stand-in: host code uses the device address that
+// hipGetSymbolAddress returns for the current device (scratch_address).
+constexpr size_t kNoAllocScratchBytes = 64ull << 20;  // 64 MiB
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
 
 thread_local std::string g_global_error;
+
+// Per-device address of `scratch`, looked up once per device with that device
+// current (each GPU holds its own copy of the array at its own address).
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;
+
+hipError_t scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = p;
+  *out = p;
+  return hipSuccess;
+}
 // Adjoint by one multi-shift solve per receiver row up to this many receivers
 // (about n_rx seed sweeps); beyond it one batched COCG over the J shifted
 // systems (about J complex solves) costs less.
@@ -76,6 +104,8 @@ struct tem_ctx {
   hipStream_t stream = nullptr;       // caller's stream (may be the null stream)
   hipStream_t work = nullptr;         // library-owned stream: every kernel runs here
   hipEvent_t order_ev = nullptr;      // orders work after the caller's stream
+  hipEvent_t done_ev = nullptr;       // orders the caller's stream after work (stream-ordered calls)
+  void* scratch = nullptr;            // this device's address of the fixed no-allocation array
   int nx = 0, ny = 0, nz = 0, ks = 0;
   std::vector<double> hx, hy, hz;
   GridArgs g{};
@@ -1209,6 +1239,9 @@ int tem_setup_grid(tem_ctx** out, int nx, int ny, int nz, const double* hx, cons
   HIPCHK(ctx, hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking));
   HIPCHK(ctx, hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming));
   HIPCHK(ctx, hipEventCreateWithFlags(&c->work_ev, hipEventDisableTiming));
+  HIPCHK(ctx, hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming));
+  // the device is current (hipSetDevice above): look up its copy of the array
+  HIPCHK(ctx, scratch_address(device, &c->scratch));
   *out = c.release();
   return TEM_OK;
 }
@@ -1623,6 +1656,40 @@ int tem_apply(tem_ctx* ctx, double shift_re, double shift_im, const double* x, d
   return TEM_OK;
 }
 
+int tem_apply_noalloc(tem_ctx* ctx, double shift_re, double shift_im, const double* x, double* y) {
+  if (!ctx) return fail(nullptr, TEM_EINVAL, "ctx is NULL");
+  if (!ctx->has_sigma) return fail(ctx, TEM_ESTATE, "conductivity not set");
+  if (!x || !y || !std::isfinite(shift_re) || !std::isfinite(shift_im)) return fail(ctx, TEM_EINVAL, "bad arguments");
+  if (x == y) return fail(ctx, TEM_EINVAL, "x and y must not alias");
+  // layout of the array: the shift (re, im) in the first 256 bytes, then the
+  // node-padded input and output, 3 nn complex values each
+  const size_t pad = (size_t)ctx->n3 * sizeof(double2);
+  const size_t need = 256 + 2 * pad;
+  if (need > kNoAllocScratchBytes)
+    return fail(ctx, TEM_EINVAL, "grid too large for tem_apply_noalloc: needs " + std::to_string(need) +
+                                     " bytes of its fixed " + std::to_string(kNoAllocScratchBytes) +
+                                     "-byte device array (2 * 3 (nx+1)(ny+1)(nz+1) * 16 + 256)");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  if (int rc = order_after_caller(ctx)) return rc;
+  hipStream_t st = ctx->work;
+  double* shv = (double*)ctx->scratch;
+  double2* xpad = (double2*)((char*)ctx->scratch + 256);
+  double2* ypad = xpad + ctx->n3;
+  // the array keeps the previous call's contents (any grid): padding entries
+  // are cleared before use, the shift is written by the stream itself
+  tem::launch_zero2(2 * ctx->n3, xpad, st);
+  tem::launch_store2(shv, shift_re, shift_im, st);
+  // y = M^1/2 (A + s) M^1/2 x = K x + s M x on interior edges (as tem_apply)
+  tem::launch_scatter_storage(ctx->g, (const double2*)x, ctx->d_sqrtm, xpad, st);
+  tem::launch_cstencil(ctx->g, xpad, 0, ctx->d_dinv, shv, shv + 1, 1, nullptr, ypad, 0, nullptr, st);
+  tem::launch_gather_storage(ctx->g, ypad, ctx->d_sqrtm, (double2*)y, st);
+  HIPCHK(ctx, hipGetLastError());
+  // later work on the caller's stream sees y
+  HIPCHK(ctx, hipEventRecord(ctx->done_ev, st));
+  HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->done_ev, 0));
+  return TEM_OK;
+}
+
 int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
   auto t_start = std::chrono::steady_clock::now();
   if (!ctx) return fail(nullptr, TEM_EINVAL, "ctx is NULL");
@@ -1992,6 +2059,7 @@ void tem_destroy(tem_ctx* ctx) {
   for (SolveSlot& sl : ctx->slots) release_slot(sl);
   if (ctx->order_ev) hipEventDestroy(ctx->order_ev);
   if (ctx->work_ev) hipEventDestroy(ctx->work_ev);
+  if (ctx->done_ev) hipEventDestroy(ctx->done_ev);
   if (ctx->work) hipStreamDestroy(ctx->work);
   delete ctx;
 }

@@ -131,6 +131,8 @@ void launch_mass(const GridArgs& g, const double* sigma_cell, double* mass, doub
                  hipStream_t s);
 void launch_scale(long long n, const double* a, const double* x, double* y, hipStream_t s);
 void launch_to_complex(long long n, const double* x, double2* y, hipStream_t s);
+void launch_zero2(long long n, double2* y, hipStream_t s);
+void launch_store2(double* p, double a, double b, hipStream_t s);
 void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, double2* Y, double2* P,
                       int J, Reduce red, SolveState* st, hipStream_t s);
 void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, double2* Y, float2* P,

@@ -953,6 +953,22 @@ __global__ void k_scale(long long n, const double* a, const double* x, double* y
   if (e < n) y[e] = a[e] * x[e];
 }
 
+// y[e] = 0 for e < n (a fill kernel rather than a memset, so that callers
+// may put it in a graph)
+__global__ void k_zero2(long long n, double2* y) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e < n) y[e] = make_double2(0.0, 0.0);
+}
+
+// p[0] = a, p[1] = b (one thread): scalars placed in device memory by the
+// stream itself, with no host staging buffer
+__global__ void k_store2(double* p, double a, double b) {
+  if (threadIdx.x == 0) {
+    p[0] = a;
+    p[1] = b;
+  }
+}
+
 __global__ void k_to_complex(long long n, const double* x, double2* y) {
   const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (e < n) y[e] = make_double2(x[e], 0.0);
@@ -1571,6 +1587,14 @@ void launch_mass(const GridArgs& g, const double* sigma_cell, double* mass, doub
 
 void launch_scale(long long n, const double* a, const double* x, double* y, hipStream_t s) {
   hipLaunchKernelGGL(k_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, a, x, y);
+}
+
+void launch_zero2(long long n, double2* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero2, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, y);
+}
+
+void launch_store2(double* p, double a, double b, hipStream_t s) {
+  hipLaunchKernelGGL(k_store2, dim3(1), dim3(64), 0, s, p, a, b);
 }
 
 void launch_to_complex(long long n, const double* x, double2* y, hipStream_t s) {

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "TEM_OK", -1: "TEM_EINVAL", -2: "TEM_ENOMEM", -3: "TEM_ENOCON
                 -4: "TEM_EBREAKDOWN", -5: "TEM_EHIP", -6: "TEM_ESTATE"}
 
 EXPORTS = ["tem_setup_grid", "tem_set_conductivity", "tem_poles", "tem_forward", "tem_adjoint",
-           "tem_solutions", "tem_apply", "tem_sizes", "tem_destroy", "tem_last_error",
+           "tem_solutions", "tem_apply", "tem_apply_noalloc", "tem_sizes", "tem_destroy", "tem_last_error",
            "tem_engine_create", "tem_attach_engine", "tem_engine_stats", "tem_engine_destroy",
            "tem_jacobian_apply"]
 
@@ -86,6 +86,7 @@ def lib():
         L.tem_jacobian_apply.argtypes = [C.c_void_p, dp, dp, C.POINTER(tem_stats)]
         L.tem_solutions.argtypes = [C.c_void_p, C.c_int, dp]
         L.tem_apply.argtypes = [C.c_void_p, C.c_double, C.c_double, dp, dp]
+        L.tem_apply_noalloc.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p]
         L.tem_sizes.argtypes = [C.c_void_p, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
         L.tem_destroy.argtypes = [C.c_void_p]
         L.tem_destroy.restype = None
@@ -282,6 +283,18 @@ class Context:
         y = np.zeros_like(x)
         _check(lib().tem_apply(self._h, float(np.real(shift)), float(np.imag(shift)), _dptr(x.view(np.float64)),
                                _dptr(y.view(np.float64))), self._h)
+        return y
+
+    def apply_noalloc(self, x, y, shift):
+        """tem_apply_noalloc: y = (K + shift M) x with x, y complex128 device
+        tensors of length n_storage (no device allocation by the library)."""
+        import torch
+        for v in (x, y):
+            if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.complex128
+                    and v.is_contiguous() and tuple(v.shape) == (self.n_storage,)):
+                raise ValueError("x and y must be contiguous complex128 device tensors of length n_storage")
+        _check(lib().tem_apply_noalloc(self._h, float(np.real(shift)), float(np.imag(shift)),
+                                       C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())), self._h)
         return y
 
     def jacobian_apply(self, dm):
