@@ -78,11 +78,44 @@ def cpu_baseline(wl, s, seconds, gpu_iterations):
         dt = time.time() - t0
     upd = float(P.n) * float(info["per_shift"].sum())
     return {"value": upd / dt, "unit": "unknown-updates/s", "cores": 1, "kind": "oracle",
+            "host_cpus": host_cpus(),
             "sample": "oracle multi-shift CG (CSR, numpy/scipy, one thread) on the same %s problem and poles, "
                       "%d seed iterations in %.1f s of the %d the GPU needs%s"
                       % (wl.name, info["iterations"], dt, gpu_iterations,
                          " (a direct factorization of one shifted system at this size does not fit in memory)"
                          if P.n > 100000 else "")}
+
+
+def host_cpus():
+    """CPUs this process may run on (the GPU machine's share of the host)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count()
+
+
+def cpu_direct_plain16(threads):
+    """The oracle's banded direct solves of the 16^3 plain workload (all J
+    shifted systems: pivoted banded LU after RCM, LAPACK gbsv) with the
+    residue contraction and receiver, wall-clock with `threads` BLAS threads."""
+    import tem_workloads as W
+    from threadpoolctl import threadpool_info, threadpool_limits
+    from oracle import direct, rkfit, yee
+    wl = W.cfg_plain16()
+    fit = rkfit.rkfit(wl.t, wl.degree)
+    s, C = rkfit.shifts_and_coefficients(fit)
+    P = yee.Problem(wl)
+    with threadpool_limits(limits=threads):
+        used = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        t0 = time.time()
+        X = direct.solve_shifted(P, s, P.F[:, 0], "banded")
+        d = P.Q @ direct.contract(X, C)
+        dt = time.time() - t0
+    upd = float(P.n) * len(s)   # one direct solve per shifted system
+    return {"value": 1.0 / dt, "unit": "models/s", "cores": int(used), "kind": "oracle",
+            "host_cpus": host_cpus(), "seconds_per_model": dt, "shifted_systems": len(s),
+            "sample": "oracle banded direct solves of the plain 16^3 workload (%d shifted systems, n = %d), "
+                      "contraction and receiver; one full model" % (len(s), P.n)}
 
 
 def serve_bench(args):
@@ -92,7 +125,7 @@ def serve_bench(args):
     import tem_workloads as W
     from paper_2506_11657_amd import tem
     from paper_2506_11657_amd.serve import Request, Server, summarize
-    trace = W.serving_trace(seed=7, n_req=args.serve)
+    trace = W.serving_trace(seed=7, n_req=args.serve_first + args.serve)[args.serve_first:]
     t = W.log_channels(1e-6, 1e-2, 40)
     xi, c, err = tem.poles(t, 44)
     torch.cuda.set_device(0)
@@ -140,33 +173,53 @@ def serve_bench(args):
 def adjoint_bench(args):
     """Differentiation workload at 64^3: blocky true and current models on the
     graded grid, 30 surface receivers, 40 channels, misfit 1/2 ||d - d_obs||^2.
-    Times one forward (solutions kept) plus the adjoint gradient w.r.t. ln sigma,
-    then checks the gradient against central differences (step 1e-3 in ln sigma)
-    of the GPU forward on seeded cells of the sensitive region, as many as the
-    time budget allows."""
+    Times one forward (solutions kept) plus the adjoint gradient w.r.t. ln sigma
+    (with --engine, the receiver-row solves share one solve engine's batched
+    launches), then checks the gradient against central differences (step
+    1e-3 in ln sigma) of the GPU forward on seeded cells of the sensitive
+    region: cells fd_first .. fd_first + fd_cells - 1 of the seeded order, as
+    many as the time budget allows.  --save-grad / --load-grad keep the
+    gradient in a .npz between runs, so that the 50 cells can be split over
+    several runs without recomputing it."""
     import tem_workloads as W
     from paper_2506_11657_amd import tem
     true_wl, cur_wl = W.cfg_inverse(64)
     xi, c, err = tem.poles(cur_wl.t, cur_wl.degree)
     t_start = time.perf_counter()
+    eng = tem.Engine(0) if args.engine else None
     ctx = tem.Context.from_workload(true_wl)
+    if eng is not None:
+        ctx.attach(eng)
     d_obs, _ = ctx.forward(true_wl.loops, true_wl.receivers, xi, c)
     print("observed data (true model) in %.1f s" % (time.perf_counter() - t_start), file=sys.stderr, flush=True)
     ctx.set_conductivity(cur_wl.sigma)
-    t0 = time.perf_counter()
-    d, st = ctx.forward(cur_wl.loops, cur_wl.receivers, xi, c, keep_solutions=True)
-    t1 = time.perf_counter()
-    g, sa = ctx.adjoint(d - d_obs)
-    t2 = time.perf_counter()
-    print("forward %.1f s (%d iterations), adjoint %.1f s (%d seed iterations over %d receiver solves)"
-          % (t1 - t0, st["iterations"], t2 - t1, sa["iterations"], len(cur_wl.receivers)), file=sys.stderr,
-          flush=True)
+    timing = {}
+    if args.load_grad:
+        z = np.load(args.load_grad)
+        g, d = z["g"], z["d"]
+        assert np.array_equal(z["d_obs"], d_obs), "stored gradient belongs to other data"
+        timing = {k: float(z[k]) for k in ("forward_s", "adjoint_s", "unknown_updates") if k in z}
+        sa_iters = None
+    else:
+        t0 = time.perf_counter()
+        d, st = ctx.forward(cur_wl.loops, cur_wl.receivers, xi, c, keep_solutions=True)
+        t1 = time.perf_counter()
+        g, sa = ctx.adjoint(d - d_obs)
+        t2 = time.perf_counter()
+        timing = {"forward_s": t1 - t0, "adjoint_s": t2 - t1,
+                  "unknown_updates": st["unknown_updates"] + sa["unknown_updates"]}
+        sa_iters = sa["iterations"]
+        print("forward %.1f s (%d iterations), adjoint %.1f s (%d seed iterations over %d receiver solves)"
+              % (t1 - t0, st["iterations"], t2 - t1, sa["iterations"], len(cur_wl.receivers)), file=sys.stderr,
+              flush=True)
+        if args.save_grad:
+            np.savez(args.save_grad, g=g, d=d, d_obs=d_obs, **timing)
     phi0 = 0.5 * float(np.sum((d - d_obs) ** 2))
     rng = np.random.default_rng(6)
     cand = np.argwhere(np.abs(g) >= 1e-2 * np.abs(g).max())
     order = rng.permutation(len(cand))
     h, checks = 1e-3, []
-    for idx in order[:args.fd_cells]:
+    for idx in order[args.fd_first:args.fd_first + args.fd_cells]:
         if time.perf_counter() - t_start > args.time_budget:
             break
         k, j, i = (int(v) for v in cand[idx])
@@ -185,15 +238,20 @@ def adjoint_bench(args):
               checks[-1]["rel_diff"]), file=sys.stderr, flush=True)
     n_unknowns = ctx.n_unknowns
     ctx.close()
-    out = {"metric": METRIC, "value": 1.0 / (t2 - t0), "unit": "gradients/s", "n_gpus": 1, "steps": 1, "warmup": 0,
-           "ms_per_step": 1e3 * (t2 - t0), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64", "data": "synthetic (seeded)",
+    if eng is not None:
+        eng.close()
+    total = timing.get("forward_s", 0.0) + timing.get("adjoint_s", 0.0)
+    out = {"metric": METRIC, "value": 1.0 / total if total > 0 else None, "unit": "gradients/s", "n_gpus": 1,
+           "steps": 1, "warmup": 0, "ms_per_step": 1e3 * total, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded)",
            "config": {"workload": "differentiation, 64^3 graded, blocky log-conductivity, 30 receivers, 40 channels",
-                      "n_unknowns": n_unknowns},
-           "forward_s": t1 - t0, "adjoint_s": t2 - t1, "misfit": phi0,
-           "unknown_updates_per_s": (st["unknown_updates"] + sa["unknown_updates"]) / (t2 - t0),
-           "fd_check": {"step_ln_sigma": h, "bar": "|fd - adj| <= 1e-4 |adj| + 1e-6 max|g|", "cells": checks,
-                        "all_pass": all(x["pass"] for x in checks)}}
+                      "n_unknowns": n_unknowns, "engine": bool(args.engine),
+                      "adjoint_path": os.environ.get("TEM_ADJOINT", "default")},
+           "forward_s": timing.get("forward_s"), "adjoint_s": timing.get("adjoint_s"), "misfit": phi0,
+           "adjoint_seed_iterations": sa_iters,
+           "unknown_updates_per_s": timing.get("unknown_updates", 0.0) / total if total > 0 else None,
+           "fd_check": {"step_ln_sigma": h, "bar": "|fd - adj| <= 1e-4 |adj| + 1e-6 max|g|",
+                        "first": args.fd_first, "cells": checks, "all_pass": all(x["pass"] for x in checks)}}
     print(json.dumps(out), flush=True)
 
 
@@ -244,7 +302,11 @@ def main():
                     help="precision 1: also time the FP64 path at this tolerance (comparison at equal accuracy)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-direct", type=int, default=1,
+                    help="also time the oracle's banded direct solves of the 16^3 workload on the host cores")
     ap.add_argument("--no-fields", action="store_true")
+    ap.add_argument("--method", type=int, default=0, choices=[0, 1],
+                    help="1: two-pass form without per-shift vectors (FP64; one pass without fields)")
     ap.add_argument("--serve", type=int, default=0,
                     help="instead of the forward benchmark, serve the first N requests of the seeded "
                          "200 req/s trace (grids 32..96, forward and adjoint, 1-4 loops)")
@@ -252,10 +314,16 @@ def main():
                     help="instead of the forward benchmark, the 64^3 differentiation workload: forward + adjoint "
                          "timing and a central-difference check of the gradient")
     ap.add_argument("--fd-cells", type=int, default=6)
+    ap.add_argument("--fd-first", type=int, default=0)
+    ap.add_argument("--engine", action="store_true", help="--adjoint: receiver-row solves through a solve engine")
+    ap.add_argument("--save-grad", default="")
+    ap.add_argument("--load-grad", default="")
     ap.add_argument("--time-budget", type=float, default=900.0, help="--adjoint: stop starting FD cells after this")
     ap.add_argument("--weights-study", action="store_true",
                     help="instead of the forward benchmark, the weighted-RKFIT evaluation on the 64^3 workload")
     ap.add_argument("--serve-max-active", type=int, default=4)
+    ap.add_argument("--serve-first", type=int, default=0,
+                    help="serve requests serve_first .. serve_first + serve - 1 of the trace")
     ap.add_argument("--serve-modes", default="batched,one_at_a_time",
                     help="comma-separated: batched (one solve engine, batched launches), overlap (own "
                          "streams and graphs per request), one_at_a_time")
@@ -292,7 +360,8 @@ def main():
         # precision 1 may stop short of rtol on stiff grids (TEM_ENOCONV): its accuracy is reported below
         return ctx.forward(wl.loops, wl.receivers, xi, c, fields=fields, block=args.block, profile=profile,
                            precision=precision, rtol=args.rtol if precision == args.precision else 0.0,
-                           refine_max=args.refine_max, allow_noconv=precision == 1)
+                           refine_max=args.refine_max, allow_noconv=precision == 1,
+                           method=args.method if precision == 0 else 0)
 
     ref = None
     if args.precision == 1:
@@ -341,7 +410,8 @@ def main():
     avg_s = ms[kind] / max(n[kind], 1) / 1e3
     J_apply = J
     nbytes = algorithmic_bytes(kind, (len(wl.hx), len(wl.hy), len(wl.hz)), J_apply, args.block, args.precision)
-    achieved = nbytes / avg_s / 1e9
+    # the two-pass form samples no kernel times (its launches are not profiled)
+    achieved = nbytes / avg_s / 1e9 if avg_s > 0 else None
     names = ["seed_stencil", "seed_update", "block_update"]
     out = {
         "metric": METRIC,
@@ -353,7 +423,8 @@ def main():
         "dtype": "f64", "data": "synthetic (seeded)",
         "config": {"workload": wl.name, "grid": list(wl.shape), "n_unknowns": ctx.n_unknowns,
                    "shifts_J": J, "channels_T": T, "degree": wl.degree, "receivers": len(wl.receivers),
-                   "block": args.block, "fields": fields is not None},
+                   "block": args.block, "fields": fields is not None,
+                   "method": "two-pass (no per-shift vectors)" if args.method == 1 else "per-shift vectors"},
         "models_per_s": args.steps / dt,
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
         "iterations": last["iterations"],
@@ -361,7 +432,8 @@ def main():
         # summed over the sampled blocks only (one block in 16 is timed with per-dispatch events)
         "kernel_ms_sampled": {names[i]: ms[i] for i in range(3)},
         "kernel_launches_sampled": {names[i]: n[i] for i in range(3)},
-        "roofline": {"bound": "hbm", "kernel": names[kind], "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": None if achieved is None else {
+                     "bound": "hbm", "kernel": names[kind], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": TRAFFIC.get((kernel_source_hash(), wl.name, names[kind])),
                      "avg_launch_us": 1e6 * avg_s, "algorithmic_bytes_per_launch": nbytes},
@@ -403,6 +475,8 @@ def main():
         out["dtype"] = "c32 search directions, f64 iterates/seed/residuals/contraction"
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, -xi, args.cpu_seconds, last["iterations"])
+        if args.cpu_direct:
+            out["cpu_baseline_direct_plain16"] = cpu_direct_plain16(min(16, host_cpus()))
     print(json.dumps(out), flush=True)
     ctx.close()
 

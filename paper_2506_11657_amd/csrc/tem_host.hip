@@ -92,8 +92,11 @@ struct SolveSlot {
   tem::SolveState* d_state = nullptr;
   void* head = nullptr;          // pinned copies of the solver head, one per block in flight
   hipStream_t stream = nullptr;  // library-owned, default priority
+  hipStream_t stream2 = nullptr; // block updates overlapped with the next blocks' seed iterations
   hipEvent_t ev = nullptr;       // orders the library stream after this slot
   hipEvent_t head_ev[2] = {nullptr, nullptr};  // head copy of block b done (b mod 2)
+  hipEvent_t sb_ev[tem::kPhases] = {};         // shift recurrences of block b done (b mod 3)
+  hipEvent_t bu_ev[tem::kPhases] = {};         // block update of block b done (b mod 3)
 };
 
 }  // namespace
@@ -141,6 +144,27 @@ struct tem_ctx {
 };
 
 namespace {
+
+// Overlap of each block's deferred update with the next block's seed
+// iterations (second stream per solve), TEM_OVERLAP=1.  Off by default: at
+// 64^3 the concurrent update slowed the latency-bound seed kernels by more
+// than it hid (5.90 s against 5.78 s per model, same box).
+// TEM_OVERLAP_BLOCKS caps the overlapped update's workgroups.
+bool overlap_updates() {
+  static const bool v = [] {
+    const char* e = getenv("TEM_OVERLAP");
+    return e && *e == '1';
+  }();
+  return v;
+}
+int overlap_blocks() {
+  static const int v = [] {
+    const char* e = getenv("TEM_OVERLAP_BLOCKS");
+    const int b = e ? atoi(e) : 0;
+    return b > 0 ? b : 4096;
+  }();
+  return v;
+}
 
 // TEM_VERBOSE=1: progress lines on stderr from long solves
 bool verbose() {
@@ -263,7 +287,10 @@ int ensure_slots(tem_ctx* ctx, int n) {
     ctx->slots.emplace_back();
     SolveSlot& sl = ctx->slots.back();
     HIPCHK(ctx, hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
+    HIPCHK(ctx, hipStreamCreateWithFlags(&sl.stream2, hipStreamNonBlocking));
     HIPCHK(ctx, hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+    for (hipEvent_t& e : sl.sb_ev) HIPCHK(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (hipEvent_t& e : sl.bu_ev) HIPCHK(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIPCHK(ctx, hipMalloc(&sl.d_state, sizeof(SolveState)));
     HIPCHK(ctx, hipHostMalloc(&sl.head, 2 * kHeadStride, hipHostMallocDefault));
     for (hipEvent_t& e : sl.head_ev) HIPCHK(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -278,6 +305,11 @@ void release_slot(SolveSlot& sl) {
   if (sl.ev) (void)hipEventDestroy(sl.ev);
   for (hipEvent_t e : sl.head_ev)
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : sl.sb_ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : sl.bu_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (sl.stream2) (void)hipStreamDestroy(sl.stream2);
   if (sl.stream) (void)hipStreamDestroy(sl.stream);
 }
 
@@ -359,6 +391,9 @@ void engine_worker(tem_engine* E) {
   int next_table = 0, parity = 0;
   bool dirty = true;
   hipError_t err = hipSuccess;
+  const auto t_start = std::chrono::steady_clock::now();
+  double next_report = 10.0;
+  long long blocks_done = 0;
   auto finish = [&](EngineJob* jb) {
     // queued after every block issued so far, which includes the job's last one
     SolveSlot& sl = jb->ctx->slots[jb->slot];
@@ -507,6 +542,15 @@ void engine_worker(tem_engine* E) {
       }
     }
     if (any) E->done_cv.notify_all();
+    ++blocks_done;
+    if (verbose()) {
+      const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+      if (el >= next_report) {
+        fprintf(stderr, "[tem] engine: %lld blocks read, %d jobs in the batch, %.1f s\n", blocks_done,
+                (int)active.size(), el);
+        next_report = el + 10.0;
+      }
+    }
   }
   // drain: nothing in flight is left behind
   (void)hipStreamSynchronize(E->stream);
@@ -559,8 +603,10 @@ int engine_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const std::
       hs.sig_im[j] = shifts_im[j];
       hs.z_re[j] = hs.zp_re[j] = 1.0;
       hs.active[j] = 1;
-      hs.apply[j] = 1;
-      hs.cf[j][0][0] = 1.0;
+      for (int f = 0; f < tem::kPhases; ++f) {
+        hs.apply[f][j] = 1;
+        hs.cf[f][j][0][0] = 1.0;
+      }
     }
     hipError_t e = hipEventCreateWithFlags(&jb.ready, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&jb.done, hipEventDisableTiming);
@@ -635,8 +681,10 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     hs->sig_im[j] = shifts_im[j];
     hs->z_re[j] = hs->zp_re[j] = 1.0;  // zeta_0 = zeta_{-1} = 1
     hs->active[j] = 1;
-    hs->apply[j] = 1;
-    hs->cf[j][0][0] = 1.0;  // a = 1, c = 0: no update before the first block
+    for (int f = 0; f < tem::kPhases; ++f) {
+      hs->apply[f][j] = 1;
+      hs->cf[f][j][0][0] = 1.0;  // a = 1, c = 0: no update before the first block
+    }
   }
   HIPCHK(ctx, hipEventRecord(ctx->work_ev, ctx->work));
   auto t0 = std::chrono::steady_clock::now();
@@ -653,15 +701,23 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     ev.resize(2 * (2 * B + 1));
     for (auto& e : ev) HIPCHK(ctx, hipEventCreate(&e));
   }
-  auto launch_block = [&](int i, bool timed, tem::Sink& st) {
+  // With overlap, block b runs its seed iterations on ring third f = b mod 3
+  // and coefficient set f, and its deferred update runs on the slot's second
+  // stream while block b+1's seed iterations proceed (the update is HBM-bound,
+  // the seed latency-bound); block b+3, which reuses third f and set f, waits
+  // for that update.  Without overlap the ring has B slots and the update ends
+  // the block's own launch sequence.
+  const bool overlap = overlap_updates();
+  const int RS = overlap ? tem::kPhases * B : B;  // ring slots
+  auto launch_block = [&](int i, bool timed, tem::Sink& st, int f) {
     SolveSlot& sl = ctx->slots[i];
     double* R = (double*)sl.R.p;
     double* pb = (double*)sl.pbuf.p;
     double* q = (double*)sl.q.p;
     const tem::Reduce red{(double*)sl.partials.p, ctx->d_counters};
     for (int l = 0; l < B; ++l) {
-      double* r = R + (size_t)l * n3;
-      double* rn = R + (size_t)((l + 1) % B) * n3;
+      double* r = R + (size_t)(f * B + l) * n3;
+      double* rn = R + (size_t)((f * B + l + 1) % RS) * n3;
       double* pold = pb + (size_t)((l + 1) & 1) * n3;
       double* pnew = pb + (size_t)(l & 1) * n3;
       tem::launch_seed_stencil(g, r, pold, pnew, q, ctx->d_dinv, s0, red, sl.d_state, l, st,
@@ -669,14 +725,33 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
       tem::launch_seed_update(g, r, q, rn, red, sl.d_state, l, st, timed ? ev[4 * l + 2] : nullptr,
                               timed ? ev[4 * l + 3] : nullptr);
     }
-    if (timed) (void)hipEventRecord(ev[4 * B], st.stream);
-    tem::launch_shift_block(g, J, red, sl.d_state, st);
-    tem::launch_block_update(g, R, Ys[i], (PV*)sl.P.p, J, B, sl.d_state, st);
-    if (timed) (void)hipEventRecord(ev[4 * B + 1], st.stream);
+    if (!overlap && timed) (void)hipEventRecord(ev[4 * B], st.stream);
+    tem::launch_shift_block(g, J, red, sl.d_state, st, f);
+    if (!overlap) {
+      tem::launch_block_update(g, R, R, Ys[i], (PV*)sl.P.p, J, B, sl.d_state, st, 0);
+      if (timed) (void)hipEventRecord(ev[4 * B + 1], st.stream);
+    }
+  };
+  // the deferred update of block b (phase f) on the second stream, after its shift recurrences
+  auto launch_update = [&](int i, bool timed, int f) -> hipError_t {
+    SolveSlot& sl = ctx->slots[i];
+    double* R = (double*)sl.R.p;
+    hipError_t e = hipEventRecord(sl.sb_ev[f], sl.stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(sl.stream2, sl.sb_ev[f], 0);
+    if (e != hipSuccess) return e;
+    if (timed) (void)hipEventRecord(ev[4 * B], sl.stream2);
+    tem::Sink d;
+    d.stream = sl.stream2;
+    tem::launch_block_update(g, R + (size_t)f * B * n3, R + (size_t)((f + 1) % tem::kPhases) * B * n3, Ys[i],
+                             (PV*)sl.P.p, J, B, sl.d_state, d, f, overlap_blocks());
+    if (timed) (void)hipEventRecord(ev[4 * B + 1], sl.stream2);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(sl.bu_ev[f], sl.stream2);
+    return e;
   };
   struct Run {
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[tem::kPhases] = {};
+    hipGraphExec_t exec[tem::kPhases] = {};
     int k = 0;             // seed iterations of the blocks whose head the host has read
     int launched = 0;      // blocks issued
     int checked = 0;       // blocks whose head the host has read
@@ -687,15 +762,16 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
   std::vector<Run> run(njobs);
   auto cleanup = [&]() {
     for (auto& e : ev) (void)hipEventDestroy(e);
-    for (Run& r : run) {
-      if (r.exec) (void)hipGraphExecDestroy(r.exec);
-      if (r.graph) (void)hipGraphDestroy(r.graph);
-    }
+    for (Run& r : run)
+      for (int f = 0; f < tem::kPhases; ++f) {
+        if (r.exec[f]) (void)hipGraphExecDestroy(r.exec[f]);
+        if (r.graph[f]) (void)hipGraphDestroy(r.graph[f]);
+      }
   };
   for (int i = 0; i < njobs; ++i) {
     SolveSlot& sl = ctx->slots[i];
     hipStream_t st = sl.stream;
-    if ((rc = ensure(ctx, sl.R, (size_t)B * n3 * sizeof(double))) ||
+    if ((rc = ensure(ctx, sl.R, (size_t)RS * n3 * sizeof(double))) ||
         (rc = ensure(ctx, sl.pbuf, 2 * n3 * sizeof(double))) || (rc = ensure(ctx, sl.q, n3 * sizeof(double))) ||
         (rc = ensure(ctx, sl.P, (size_t)J * n3 * sizeof(double2))) ||
         (rc = ensure(ctx, sl.partials, 2 * (size_t)tem::kReduceSlots * sizeof(double)))) {
@@ -723,20 +799,25 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     // stream capture: a capture could be invalidated by a device-wide call such
     // as hipFree from another request's thread); on failure the blocks are
     // launched directly
-    tem::Sink gk;
-    hipError_t ge = hipGraphCreate(&run[i].graph, 0);
-    if (ge == hipSuccess) {
-      gk.graph = run[i].graph;
-      launch_block(i, false, gk);
-      ge = gk.err;
+    hipError_t ge = hipSuccess;
+    for (int f = 0; f < (overlap ? tem::kPhases : 1) && ge == hipSuccess; ++f) {
+      tem::Sink gk;
+      ge = hipGraphCreate(&run[i].graph[f], 0);
+      if (ge == hipSuccess) {
+        gk.graph = run[i].graph[f];
+        launch_block(i, false, gk, f);
+        ge = gk.err;
+      }
+      if (ge == hipSuccess) ge = hipGraphInstantiate(&run[i].exec[f], run[i].graph[f], nullptr, nullptr, 0);
     }
-    if (ge == hipSuccess) ge = hipGraphInstantiate(&run[i].exec, run[i].graph, nullptr, nullptr, 0);
     if (ge != hipSuccess) {
       (void)hipGetLastError();
-      if (run[i].exec) (void)hipGraphExecDestroy(run[i].exec);
-      if (run[i].graph) (void)hipGraphDestroy(run[i].graph);
-      run[i].graph = nullptr;
-      run[i].exec = nullptr;
+      for (int f = 0; f < tem::kPhases; ++f) {
+        if (run[i].exec[f]) (void)hipGraphExecDestroy(run[i].exec[f]);
+        if (run[i].graph[f]) (void)hipGraphDestroy(run[i].graph[f]);
+        run[i].graph[f] = nullptr;
+        run[i].exec[f] = nullptr;
+      }
       if (verbose()) fprintf(stderr, "[tem] solver block graph not built (%s): direct launches\n", hipGetErrorString(ge));
     }
   }
@@ -749,15 +830,19 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     SolveSlot& sl = ctx->slots[i];
     Run& r = run[i];
     const bool timed = o.profile && i == 0 && r.launched % kProfileEvery == 0;
+    const int f = overlap ? r.launched % tem::kPhases : 0;
     hipError_t e = hipSuccess;
-    if (r.exec && !timed) {
-      e = hipGraphLaunch(r.exec, sl.stream);
-    } else {
+    // block b reuses ring third and coefficient set f after block b-3's update
+    if (overlap && r.launched >= tem::kPhases) e = hipStreamWaitEvent(sl.stream, sl.bu_ev[f], 0);
+    if (e == hipSuccess && r.exec[f] && !timed) {
+      e = hipGraphLaunch(r.exec[f], sl.stream);
+    } else if (e == hipSuccess) {
       tem::Sink direct;
       direct.stream = sl.stream;
-      launch_block(i, timed, direct);
+      launch_block(i, timed, direct, f);
     }
     if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess && overlap) e = launch_update(i, timed, f);
     const int h = r.launched & 1;
     if (e == hipSuccess)
       e = hipMemcpyAsync((char*)sl.head + h * kHeadStride, sl.d_state, sizeof(tem::SolveHead),
@@ -807,6 +892,7 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
           ctx->prof_ms[TEM_K_UPDATE] += b;
         }
         float c = 0.f;
+        (void)hipEventSynchronize(ev[4 * B + 1]);  // with overlap the update ends on the second stream
         (void)hipEventElapsedTime(&c, ev[4 * B], ev[4 * B + 1]);
         ctx->prof_ms[TEM_K_BLOCK] += c;
         ctx->prof_n[TEM_K_STENCIL] += B;
@@ -825,7 +911,10 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
   }
   if (lerr != hipSuccess) {
     // blocks still in flight finish before their graphs and events are destroyed
-    for (int i = 0; i < njobs; ++i) (void)hipStreamSynchronize(ctx->slots[i].stream);
+    for (int i = 0; i < njobs; ++i) {
+      (void)hipStreamSynchronize(ctx->slots[i].stream);
+      (void)hipStreamSynchronize(ctx->slots[i].stream2);
+    }
     cleanup();
     return fail(ctx, TEM_EHIP, std::string("solver loop: ") + hipGetErrorString(lerr));
   }
@@ -833,6 +922,9 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
   hipError_t fe = hipSuccess;
   for (int i = 0; i < njobs; ++i) {
     SolveSlot& sl = ctx->slots[i];
+    // the last block's update (second stream) precedes everything that reads Y
+    if (overlap && run[i].launched > 0)
+      fe = hipStreamWaitEvent(sl.stream, sl.bu_ev[(run[i].launched - 1) % tem::kPhases], 0);
     if (fe == hipSuccess)
       fe = hipMemcpyAsync(&states[i], sl.d_state, sizeof(SolveState), hipMemcpyDeviceToHost, sl.stream);
     // also waits for a block issued after the last one the host read
@@ -982,8 +1074,10 @@ int lanczos_source(tem_ctx* ctx, int i, const std::vector<double>& shifts_re, co
     hs->sig_im[j] = shifts_im[j];
     hs->z_re[j] = hs->zp_re[j] = 1.0;
     hs->active[j] = 1;
-    hs->apply[j] = 1;
-    hs->cf[j][0][0] = 1.0;
+    for (int f = 0; f < tem::kPhases; ++f) {
+      hs->apply[f][j] = 1;
+      hs->cf[f][j][0][0] = 1.0;
+    }
   }
   // the leading part of the state up to and including this block's history
   const size_t hist_bytes = offsetof(SolveState, carry_alpha);
@@ -1715,11 +1809,20 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
     for (DevBuf* b : {&H, &Mu, &Rr, &Pb, &Q, &z, &gd, &gam, &cst}) release(*b);
   };
   const long long ncell = (long long)ctx->nx * ctx->ny * ctx->nz;
-  const int nH = n_rx <= kAdjointMultishiftMaxRx ? std::min(n_rx, kMaxConcurrentSolves) : 1;
+  // receiver-row multi-shift solves (up to kAdjointMultishiftMaxRx receivers)
+  // or one batched COCG; TEM_ADJOINT=cocg / multishift forces either.  With a
+  // solve engine attached, up to kMaxBatchJobs rows share its batched launches.
+  bool use_rows = n_rx <= kAdjointMultishiftMaxRx;
+  if (const char* m = getenv("TEM_ADJOINT")) {
+    if (!strcmp(m, "cocg")) use_rows = false;
+    if (!strcmp(m, "multishift")) use_rows = true;
+  }
+  const int row_conc = std::min(n_rx, ctx->engine ? tem::kMaxBatchJobs : kMaxConcurrentSolves);
+  const int nH = use_rows ? row_conc : 1;
   if ((rc = ensure(ctx, H, nH * vb)) || (rc = ensure(ctx, Mu, vb)) || (rc = ensure(ctx, Rr, vb)) ||
       (rc = ensure(ctx, Pb, 2 * vb)) || (rc = ensure(ctx, Q, vb)) || (rc = ensure(ctx, z, ctx->n3 * sizeof(double))) ||
       (rc = ensure(ctx, gd, ncell * sizeof(double))) || (rc = ensure(ctx, gam, 2 * (size_t)J * n_rx * sizeof(double))) ||
-      (rc = ensure(ctx, cst, (size_t)(2 * TEM_MAX_SHIFTS * kMaxConcurrentSolves * sizeof(double))))) {
+      (rc = ensure(ctx, cst, (size_t)(2 * TEM_MAX_SHIFTS * tem::kMaxBatchJobs * sizeof(double))))) {
     cleanup();
     return rc;
   }
@@ -1783,7 +1886,7 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
       }
       for (int j = 0; j < J; ++j) S.unknown_updates += (double)ctx->nunk * fst.iters[j];
     }
-    if (n_rx <= kAdjointMultishiftMaxRx) {
+    if (use_rows) {
       // lambda_j = sum_r gamma_jr (K + s_j M)^-1 q_r: one multi-shift solve per
       // receiver row (all shifts share its Krylov recurrence), up to
       // kMaxConcurrentSolves rows at once, combined on the device
@@ -1793,7 +1896,7 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
         sre[j] = -ctx->fwd_xi[2 * j];
         sim[j] = -ctx->fwd_xi[2 * j + 1];
       }
-      const int nconc = std::min(n_rx, kMaxConcurrentSolves);
+      const int nconc = row_conc;
       if ((rc = ensure_slots(ctx, nconc))) {
         cleanup();
         return rc;
@@ -2047,8 +2150,10 @@ void tem_destroy(tem_ctx* ctx) {
   if (!ctx) return;
   hipSetDevice(ctx->device);
   if (ctx->work) hipStreamSynchronize(ctx->work);
-  for (SolveSlot& sl : ctx->slots)
+  for (SolveSlot& sl : ctx->slots) {
     if (sl.stream) hipStreamSynchronize(sl.stream);
+    if (sl.stream2) hipStreamSynchronize(sl.stream2);
+  }
   for (double* p : {ctx->d_axis, ctx->d_sigma, ctx->d_mass, ctx->d_dinv, ctx->d_sqrtm})
     if (p) hipFree(p);
   if (ctx->d_counters) hipFree(ctx->d_counters);

@@ -15,6 +15,9 @@ constexpr double kMu0 = 4e-7 * 3.14159265358979323846;  // Sec. 2.1
 constexpr int kMaxShifts = 64;
 constexpr int kMaxBlock = 64;       // deferred-update block length (iterations)
 constexpr int kReduceSlots = 65536;  // per-kernel partial sums (upper bound on stencil blocks)
+// block-coefficient sets: with the block update overlapped with the next
+// blocks' seed iterations, block b uses set b mod 3 (and ring third b mod 3)
+constexpr int kPhases = 3;
 
 // Node-padded layout: every node (i, j, k), 0 <= i <= nx, ... owns the three
 // edges Ex(i,j,k), Ey(i,j,k), Ez(i,j,k) leaving it in +x, +y, +z.  Edges that
@@ -57,13 +60,13 @@ struct SolveState {
   double sig_re[kMaxShifts], sig_im[kMaxShifts];    // s_j - s0
   double z_re[kMaxShifts], z_im[kMaxShifts];        // zeta_k
   double zp_re[kMaxShifts], zp_im[kMaxShifts];      // zeta_{k-1}
-  int apply[kMaxShifts];                            // updated at least once in this block
+  int apply[kPhases][kMaxShifts];                   // updated at least once in this block
   int iters[kMaxShifts];
   double est[kMaxShifts];                           // |zeta| ||r|| at the stop
   // block coefficients: p_new = a p + sum_l e_l r_l ; y_new = y + c p + sum_l d_l r_l,
-  // packed per shift for uniform reads: cf[j][0] = (a, c), cf[j][1 + l] = (e_l, d_l),
-  // each complex as (re, im)
-  double cf[kMaxShifts][kMaxBlock + 1][4];
+  // packed per shift for uniform reads: cf[f][j][0] = (a, c), cf[f][j][1 + l] = (e_l, d_l),
+  // each complex as (re, im); f is the block's coefficient set
+  double cf[kPhases][kMaxShifts][kMaxBlock + 1][4];
 };
 
 struct SolveHead {  // the leading part of SolveState
@@ -143,16 +146,18 @@ void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold,
                          hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_seed_update(const GridArgs& g, const double* r, const double* q, double* rnext, Reduce red,
                         SolveState* st, int local, Sink& k, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
-void launch_block_update(const GridArgs& g, const double* R, double2* Y, double2* P, int J, int B,
-                         const SolveState* st, Sink& k);
+// R: the block's ring part (slot l holds r_{k0+l}, l = 1 .. B-1), R0: the slot
+// holding r_{k0+B}; coefficient set f
+void launch_block_update(const GridArgs& g, const double* R, const double* R0, double2* Y, double2* P, int J, int B,
+                         const SolveState* st, Sink& k, int f = 0, int max_blocks = 4096);
 // precision 1: y_j in FP64, p_j in FP32
-void launch_block_update(const GridArgs& g, const double* R, double2* Y, float2* P, int J, int B,
-                         const SolveState* st, Sink& k);
+void launch_block_update(const GridArgs& g, const double* R, const double* R0, double2* Y, float2* P, int J, int B,
+                         const SolveState* st, Sink& k, int f = 0, int max_blocks = 4096);
 // J node-padded complex vectors, FP32 storage widened to FP64: sign 0 sets
 // Y_j = X_j for all j; sign +1 / -1 adds / subtracts X_j for the j in mask
 void launch_accumulate(const GridArgs& g, int J, const float2* X, double2* Y, int sign, unsigned long long mask,
                        hipStream_t s);
-void launch_shift_block(const GridArgs& g, int J, Reduce red, SolveState* st, Sink& k);
+void launch_shift_block(const GridArgs& g, int J, Reduce red, SolveState* st, Sink& k, int f = 0);
 void launch_cstencil(const GridArgs& g, const double2* X, long long xstride, const double* dinv,
                      const double* shift_re, const double* shift_im, int nvec, const double2* rhs,
                      double2* out, long long ostride, double* norm_partials, hipStream_t s);

@@ -636,7 +636,8 @@ __global__ void __launch_bounds__(UPD_T) k_seed_update(long long n, const double
 //   alpha^s_k = a_k zeta_{k+1}/zeta_k,  beta^s_k = b_k (zeta_{k+1}/zeta_k)^2,
 //   y_{k+1} = y_k + alpha^s_k p_k,  p_{k+1} = zeta_{k+1} r_{k+1} + beta^s_k p_k,
 // accumulated as coefficients of the block's starting p and residuals r_l.
-__device__ __forceinline__ void shift_block_wave(const double* __restrict__ upd_partials, SolveState* st, int j) {
+__device__ __forceinline__ void shift_block_wave(const double* __restrict__ upd_partials, SolveState* st, int j,
+                                                 int f) {
   const int lane = threadIdx.x;
   constexpr int NPART = (UPD_BLOCKS + kWave - 1) / kWave;
   __shared__ double red[1];
@@ -659,7 +660,7 @@ __device__ __forceinline__ void shift_block_wave(const double* __restrict__ upd_
     st->k += B;
   }
   if (!is_active) {
-    if (lane == 0) st->apply[j] = 0;
+    if (lane == 0) st->apply[f][j] = 0;
     return;
   }
   const double tol2 = st->tol2;
@@ -711,15 +712,15 @@ __device__ __forceinline__ void shift_block_wave(const double* __restrict__ upd_
     if (est2 <= tol2) active = false;
   }
   if (lane < B) {
-    double* cl = st->cf[j][1 + lane];
+    double* cl = st->cf[f][j][1 + lane];
     cl[0] = e.re;
     cl[1] = e.im;
     cl[2] = d.re;
     cl[3] = d.im;
   }
   if (lane == 0) {
-    st->apply[j] = 1;
-    double* c0 = st->cf[j][0];
+    st->apply[f][j] = 1;
+    double* c0 = st->cf[f][j][0];
     c0[0] = a.re;
     c0[1] = a.im;
     c0[2] = c.re;
@@ -735,8 +736,8 @@ __device__ __forceinline__ void shift_block_wave(const double* __restrict__ upd_
   }
 }
 
-__global__ void __launch_bounds__(64) k_shift_block(const double* __restrict__ upd_partials, SolveState* st) {
-  shift_block_wave(upd_partials, st, blockIdx.x);
+__global__ void __launch_bounds__(64) k_shift_block(const double* __restrict__ upd_partials, SolveState* st, int f) {
+  shift_block_wave(upd_partials, st, blockIdx.x, f);
 }
 
 // Deferred shift update after a block of BB seed iterations:
@@ -751,16 +752,18 @@ __global__ void __launch_bounds__(64) k_shift_block(const double* __restrict__ u
 // writes nothing the coefficients could alias.
 constexpr int BU_T = 256;
 template <int BB, typename YV, typename PV>
-__device__ __forceinline__ void block_update_block(long long n3, const double* __restrict__ R, YV* __restrict__ Y,
+__device__ __forceinline__ void block_update_block(long long n3, const double* __restrict__ R,
+                                                  const double* __restrict__ R0, YV* __restrict__ Y,
                                                   PV* __restrict__ P, int J, const SolveState* __restrict__ st,
-                                                  int blk, int nblk) {
+                                                  int f, int blk, int nblk) {
   for (long long e = blk * (long long)BU_T + threadIdx.x; e < n3; e += (long long)nblk * BU_T) {
     double rl[BB];
+    rl[0] = R0[e];
 #pragma unroll
-    for (int l = 0; l < BB; ++l) rl[l] = R[(long long)l * n3 + e];
+    for (int l = 1; l < BB; ++l) rl[l] = R[(long long)l * n3 + e];
     for (int j = 0; j < J; ++j) {
-      if (!st->apply[j]) continue;
-      const double* c = st->cf[j][0];
+      if (!st->apply[f][j]) continue;
+      const double* c = st->cf[f][j][0];
       const cplx p = ldv(P, (long long)j * n3 + e);
       const cplx y = ldv(Y, (long long)j * n3 + e);
       double pr = c[0] * p.re - c[1] * p.im;
@@ -782,10 +785,11 @@ __device__ __forceinline__ void block_update_block(long long n3, const double* _
 }
 
 template <int BB, typename YV, typename PV>
-__global__ void __launch_bounds__(BU_T) k_block_update(long long n3, const double* __restrict__ R, YV* __restrict__ Y,
+__global__ void __launch_bounds__(BU_T) k_block_update(long long n3, const double* __restrict__ R,
+                                                       const double* __restrict__ R0, YV* __restrict__ Y,
                                                        PV* __restrict__ P, int J,
-                                                       const SolveState* __restrict__ st) {
-  block_update_block<BB, YV, PV>(n3, R, Y, P, J, st, blockIdx.x, gridDim.x);
+                                                       const SolveState* __restrict__ st, int f) {
+  block_update_block<BB, YV, PV>(n3, R, R0, Y, P, J, st, f, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -820,7 +824,7 @@ __global__ void __launch_bounds__(UPD_T) k_seed_update_batch(const BatchJob* __r
 __global__ void __launch_bounds__(64) k_shift_block_batch(const BatchJob* __restrict__ jobs) {
   const BatchJob& jb = jobs[blockIdx.y];
   if ((int)blockIdx.x >= jb.J) return;
-  shift_block_wave(jb.part_up, jb.st, blockIdx.x);
+  shift_block_wave(jb.part_up, jb.st, blockIdx.x, 0);
 }
 
 template <int BB>
@@ -828,8 +832,8 @@ __global__ void __launch_bounds__(BU_T) k_block_update_batch(const BatchJob* __r
   int j = 0;
   while (j + 1 < njobs && (int)blockIdx.x >= jobs[j + 1].bu0) ++j;
   const BatchJob& jb = jobs[j];
-  block_update_block<BB, double2, double2>(3 * jb.g.nn, jb.R, jb.Y, jb.P, jb.J, jb.st, (int)blockIdx.x - jb.bu0,
-                                           jb.nbu);
+  block_update_block<BB, double2, double2>(3 * jb.g.nn, jb.R, jb.R, jb.Y, jb.P, jb.J, jb.st, 0,
+                                           (int)blockIdx.x - jb.bu0, jb.nbu);
 }
 
 // the leading SolveHead of every job's state, contiguous, for one copy to the host
@@ -1745,9 +1749,9 @@ int seed_stencil_blocks(const GridArgs& g) {
   return sg.x * sg.y * sg.z;
 }
 
-void launch_shift_block(const GridArgs& g, int J, Reduce red, SolveState* st, Sink& k) {
+void launch_shift_block(const GridArgs& g, int J, Reduce red, SolveState* st, Sink& k, int f) {
   (void)g;
-  put(k, k_shift_block, dim3(J), dim3(64), 0u, nullptr, nullptr, (const double*)(red.partials + kReduceSlots), st);
+  put(k, k_shift_block, dim3(J), dim3(64), 0u, nullptr, nullptr, (const double*)(red.partials + kReduceSlots), st, f);
 }
 
 void launch_seed_stencil_batch(const BatchJob* jobs, int njobs, int total_tiles, int B, int local, Sink& k) {
@@ -1778,24 +1782,24 @@ void launch_gather_heads(const BatchJob* jobs, int njobs, SolveHead* out, Sink& 
 
 
 template <typename YV, typename PV>
-static void block_update(const GridArgs& g, const double* R, YV* Y, PV* P, int J, int B, const SolveState* st,
-                         Sink& k) {
+static void block_update(const GridArgs& g, const double* R, const double* R0, YV* Y, PV* P, int J, int B,
+                         const SolveState* st, Sink& k, int f, int max_blocks) {
   const long long n3 = 3 * g.nn;
-  const dim3 grid(grid_1d(n3, BU_T, 4096)), block(BU_T);
+  const dim3 grid(grid_1d(n3, BU_T, max_blocks)), block(BU_T);
   switch (B) {
-    case 16: put(k, k_block_update<16, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, Y, P, J, st); break;
-    case 32: put(k, k_block_update<32, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, Y, P, J, st); break;
-    case 64: put(k, k_block_update<64, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, Y, P, J, st); break;
-    default: put(k, k_block_update<8, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, Y, P, J, st); break;
+    case 16: put(k, k_block_update<16, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, R0, Y, P, J, st, f); break;
+    case 32: put(k, k_block_update<32, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, R0, Y, P, J, st, f); break;
+    case 64: put(k, k_block_update<64, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, R0, Y, P, J, st, f); break;
+    default: put(k, k_block_update<8, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, R0, Y, P, J, st, f); break;
   }
 }
-void launch_block_update(const GridArgs& g, const double* R, double2* Y, double2* P, int J, int B,
-                         const SolveState* st, Sink& k) {
-  block_update(g, R, Y, P, J, B, st, k);
+void launch_block_update(const GridArgs& g, const double* R, const double* R0, double2* Y, double2* P, int J, int B,
+                         const SolveState* st, Sink& k, int f, int max_blocks) {
+  block_update(g, R, R0, Y, P, J, B, st, k, f, max_blocks);
 }
-void launch_block_update(const GridArgs& g, const double* R, double2* Y, float2* P, int J, int B,
-                         const SolveState* st, Sink& k) {
-  block_update(g, R, Y, P, J, B, st, k);
+void launch_block_update(const GridArgs& g, const double* R, const double* R0, double2* Y, float2* P, int J, int B,
+                         const SolveState* st, Sink& k, int f, int max_blocks) {
+  block_update(g, R, R0, Y, P, J, B, st, k, f, max_blocks);
 }
 
 void launch_accumulate(const GridArgs& g, int J, const float2* X, double2* Y, int sign, unsigned long long mask,

@@ -24,6 +24,7 @@ result is bitwise the same alone or in any mix.
 """
 from __future__ import annotations
 
+import os
 import sys
 import threading
 import time
@@ -37,7 +38,7 @@ from . import tem
 def footprint_bytes(nx, ny, nz, J, n_src, kind, block=64, n_rx=1, concurrent=4):
     """Device bytes a request needs (the library's allocations for it):
     operator arrays; one solver workspace per concurrent multi-shift solve
-    (residual ring of `block` vectors, seed p and q, right-hand side, per-shift
+    (residual ring of `block` vectors, 3x that with overlapped updates, seed p and q, right-hand side, per-shift
     p_j); the solutions y_j of every concurrent source (of every source for the
     adjoint, which keeps them); the residual and contraction scratch; for the
     adjoint, its right-hand sides per concurrent receiver row and its COCG
@@ -49,7 +50,8 @@ def footprint_bytes(nx, ny, nz, J, n_src, kind, block=64, n_rx=1, concurrent=4):
     slots = conc
     if kind == "adjoint":
         slots = max(slots, min(n_rx, concurrent))
-    slot = 8 * n3 * (block + 4) + vec + (1 << 20)
+    ring = 3 * block if os.environ.get("TEM_OVERLAP") == "1" else block   # 3 blocks with overlapped updates
+    slot = 8 * n3 * (ring + 4) + vec + (1 << 20)
     keep = vec * (n_src if kind == "adjoint" else conc)
     scratch = vec + 24 * n3
     adj = 0
@@ -179,4 +181,7 @@ def summarize(requests, wall):
             "models_per_s": len(done) / wall if wall > 0 else 0.0,
             "unknown_updates_per_s": upd / wall if wall > 0 else 0.0,
             "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
-            "makespan_s": wall}
+            "makespan_s": wall,
+            # per request: (arrival, admitted, finished) in seconds from the start
+            "requests": [(r.rid, r.kind, len(r.workload.hx), len(r.workload.loops), r.arrival, r.admitted, r.finished)
+                         for r in requests]}
