@@ -113,8 +113,10 @@ typedef struct {
 } tem_solve_opts;
 
 /* kernel classes reported by tem_stats.kernel_ms */
-#define TEM_K_STENCIL 0     /* seed stencil: p = r + beta p; q = (A + s0) p; (p, q) */
-#define TEM_K_UPDATE 1      /* seed update: r -= alpha q; (r, r); shifted recurrences */
+#define TEM_K_STENCIL 0     /* seed stencil: p = r + beta p; q = (A + s0) p; (p, q).  In the one-kernel
+                               form (the default) the whole seed step: r -= alpha q; p = r + beta p;
+                               q = (A + s0) p; four inner products */
+#define TEM_K_UPDATE 1      /* seed update: r -= alpha q; (r, r) (two-kernel form only) */
 #define TEM_K_BLOCK 2       /* deferred shift update of x_j, p_j every block */
 #define TEM_K_OTHER 3       /* init, true residual, contraction, receivers */
 

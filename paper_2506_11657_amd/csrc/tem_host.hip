@@ -129,6 +129,7 @@ struct tem_ctx {
   DevBuf refine64, refdot;             // precision 1: FP64 corrections d_j and (A + s_j) d_j; step lengths
   std::vector<DevBuf> Y;  // per source (kept) or one
   // stored forward state for the adjoint
+  bool seed_one_kernel = true;  // seed CG in one kernel per iteration (else stencil + update)
   bool fwd_meta = false;   // the last forward's sources, receivers, poles and options are recorded
   bool fwd_valid = false;  // ... and its solutions are kept on the device
   int fwd_J = 0, fwd_T = 0, fwd_nsrc = 0, fwd_nrx = 0;
@@ -164,6 +165,15 @@ int overlap_blocks() {
     return b > 0 ? b : 4096;
   }();
   return v;
+}
+
+// Seed CG form of a context's solves, fixed when the context is created: one
+// kernel per iteration (update fused with the next stencil, the default) or
+// the two-kernel stencil + update form (TEM_SEED=hs).  The batched engine uses
+// the two-kernel form.
+bool seed_one_kernel_env() {
+  const char* e = getenv("TEM_SEED");
+  return !(e && e[0] == 'h' && e[1] == 's');
 }
 
 // TEM_VERBOSE=1: progress lines on stderr from long solves
@@ -708,7 +718,10 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
   // for that update.  Without overlap the ring has B slots and the update ends
   // the block's own launch sequence.
   const bool overlap = overlap_updates();
+  const bool one_kernel = ctx->seed_one_kernel;
   const int RS = overlap ? tem::kPhases * B : B;  // ring slots
+  // pbuf: p_{k-1}, p_k by parity (two-kernel form), or p_i, p_{i+1} and then
+  // q_i, q_{i+1} by parity (one-kernel form)
   auto launch_block = [&](int i, bool timed, tem::Sink& st, int f) {
     SolveSlot& sl = ctx->slots[i];
     double* R = (double*)sl.R.p;
@@ -720,13 +733,21 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
       double* rn = R + (size_t)((f * B + l + 1) % RS) * n3;
       double* pold = pb + (size_t)((l + 1) & 1) * n3;
       double* pnew = pb + (size_t)(l & 1) * n3;
+      if (one_kernel) {
+        tem::launch_seed_step(g, r, pb + (size_t)(l & 1) * n3, pb + (size_t)(2 + (l & 1)) * n3, rn,
+                              pb + (size_t)((l + 1) & 1) * n3, pb + (size_t)(2 + ((l + 1) & 1)) * n3, ctx->d_dinv,
+                              s0, red, sl.d_state, l, 0, st, timed ? ev[4 * l] : nullptr,
+                              timed ? ev[4 * l + 1] : nullptr);
+        continue;
+      }
       tem::launch_seed_stencil(g, r, pold, pnew, q, ctx->d_dinv, s0, red, sl.d_state, l, st,
                                timed ? ev[4 * l] : nullptr, timed ? ev[4 * l + 1] : nullptr);
       tem::launch_seed_update(g, r, q, rn, red, sl.d_state, l, st, timed ? ev[4 * l + 2] : nullptr,
                               timed ? ev[4 * l + 3] : nullptr);
     }
     if (!overlap && timed) (void)hipEventRecord(ev[4 * B], st.stream);
-    tem::launch_shift_block(g, J, red, sl.d_state, st, f);
+    if (one_kernel) tem::launch_shift_block_step(g, J, red, sl.d_state, st, f);
+    else tem::launch_shift_block(g, J, red, sl.d_state, st, f);
     if (!overlap) {
       tem::launch_block_update(g, R, R, Ys[i], (PV*)sl.P.p, J, B, sl.d_state, st, 0);
       if (timed) (void)hipEventRecord(ev[4 * B + 1], st.stream);
@@ -772,9 +793,10 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     SolveSlot& sl = ctx->slots[i];
     hipStream_t st = sl.stream;
     if ((rc = ensure(ctx, sl.R, (size_t)RS * n3 * sizeof(double))) ||
-        (rc = ensure(ctx, sl.pbuf, 2 * n3 * sizeof(double))) || (rc = ensure(ctx, sl.q, n3 * sizeof(double))) ||
+        (rc = ensure(ctx, sl.pbuf, (one_kernel ? 4 : 2) * n3 * sizeof(double))) ||
+        (rc = ensure(ctx, sl.q, n3 * sizeof(double))) ||
         (rc = ensure(ctx, sl.P, (size_t)J * n3 * sizeof(double2))) ||
-        (rc = ensure(ctx, sl.partials, 2 * (size_t)tem::kReduceSlots * sizeof(double)))) {
+        (rc = ensure(ctx, sl.partials, 8 * (size_t)tem::kReduceSlots * sizeof(double)))) {
       cleanup();
       return rc;
     }
@@ -788,6 +810,13 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
       const tem::Reduce red{(double*)sl.partials.p, ctx->d_counters};
       tem::launch_seed_init(g, (const double*)sl.gvec.p, (double*)sl.R.p, (double*)sl.pbuf.p + n3, Ys[i],
                             (PV*)sl.P.p, J, red, sl.d_state, st);
+      if (one_kernel) {  // p_0 = r_0, q_0 = A0 r_0 into slot 0 and the partials of step 0
+        tem::Sink pro;
+        pro.stream = st;
+        const double* r0 = (const double*)sl.R.p;
+        tem::launch_seed_step(g, r0, r0, r0, nullptr, (double*)sl.pbuf.p, (double*)sl.pbuf.p + 2 * n3,
+                              ctx->d_dinv, s0, red, sl.d_state, 0, 1, pro);
+      }
       se = hipGetLastError();
     }
     if (se != hipSuccess) {
@@ -887,16 +916,16 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
         for (int l = 0; l < B; ++l) {
           float a = 0.f, b = 0.f;
           (void)hipEventElapsedTime(&a, ev[4 * l], ev[4 * l + 1]);
-          (void)hipEventElapsedTime(&b, ev[4 * l + 2], ev[4 * l + 3]);
+          if (!one_kernel) (void)hipEventElapsedTime(&b, ev[4 * l + 2], ev[4 * l + 3]);
           ctx->prof_ms[TEM_K_STENCIL] += a;
-          ctx->prof_ms[TEM_K_UPDATE] += b;
+          if (!one_kernel) ctx->prof_ms[TEM_K_UPDATE] += b;
         }
         float c = 0.f;
         (void)hipEventSynchronize(ev[4 * B + 1]);  // with overlap the update ends on the second stream
         (void)hipEventElapsedTime(&c, ev[4 * B], ev[4 * B + 1]);
         ctx->prof_ms[TEM_K_BLOCK] += c;
         ctx->prof_n[TEM_K_STENCIL] += B;
-        ctx->prof_n[TEM_K_UPDATE] += B;
+        if (!one_kernel) ctx->prof_n[TEM_K_UPDATE] += B;
         ctx->prof_n[TEM_K_BLOCK] += 1;
       }
     }
@@ -1046,9 +1075,11 @@ int lanczos_source(tem_ctx* ctx, int i, const std::vector<double>& shifts_re, co
   hipStream_t st = ctx->work;
   int rc;
   SolveSlot& sl = ctx->slots[i];
+  const bool one_kernel = ctx->seed_one_kernel;
   if ((rc = ensure(ctx, sl.R, (size_t)B * n3 * sizeof(double))) ||
-      (rc = ensure(ctx, sl.pbuf, 2 * n3 * sizeof(double))) || (rc = ensure(ctx, sl.q, n3 * sizeof(double))) ||
-      (rc = ensure(ctx, sl.partials, 2 * (size_t)tem::kReduceSlots * sizeof(double))))
+      (rc = ensure(ctx, sl.pbuf, (one_kernel ? 4 : 2) * n3 * sizeof(double))) ||
+      (rc = ensure(ctx, sl.q, n3 * sizeof(double))) ||
+      (rc = ensure(ctx, sl.partials, 8 * (size_t)tem::kReduceSlots * sizeof(double))))
     return rc;
   const int nrx = std::max(n_rx, 1);
   DevBuf hqd, Wd, Ud;
@@ -1092,6 +1123,11 @@ int lanczos_source(tem_ctx* ctx, int i, const std::vector<double>& shifts_re, co
     if (e != hipSuccess) return e;
     tem::launch_seed_init(g, (const double*)sl.gvec.p, R, pb + n3, (double2*)nullptr, (double2*)nullptr, 0, red,
                           sl.d_state, st);
+    if (one_kernel) {
+      tem::Sink pro;
+      pro.stream = st;
+      tem::launch_seed_step(g, R, R, R, nullptr, pb, pb + 2 * n3, ctx->d_dinv, s0, red, sl.d_state, 0, 1, pro);
+    }
     return hipGetLastError();
   };
   // the seed kernels of one block plus the shift recurrences (convergence and
@@ -1102,11 +1138,20 @@ int lanczos_source(tem_ctx* ctx, int i, const std::vector<double>& shifts_re, co
     tem::Sink k;
     k.graph = *gr;
     for (int l = 0; l < B; ++l) {
-      tem::launch_seed_stencil(g, R + (size_t)l * n3, pb + (size_t)((l + 1) & 1) * n3, pb + (size_t)(l & 1) * n3, q,
-                               ctx->d_dinv, s0, red, sl.d_state, l, k);
-      tem::launch_seed_update(g, R + (size_t)l * n3, q, R + (size_t)((l + 1) % B) * n3, red, sl.d_state, l, k);
+      double* r = R + (size_t)l * n3;
+      double* rn = R + (size_t)((l + 1) % B) * n3;
+      if (one_kernel) {
+        tem::launch_seed_step(g, r, pb + (size_t)(l & 1) * n3, pb + (size_t)(2 + (l & 1)) * n3, rn,
+                              pb + (size_t)((l + 1) & 1) * n3, pb + (size_t)(2 + ((l + 1) & 1)) * n3, ctx->d_dinv, s0,
+                              red, sl.d_state, l, 0, k);
+        continue;
+      }
+      tem::launch_seed_stencil(g, r, pb + (size_t)((l + 1) & 1) * n3, pb + (size_t)(l & 1) * n3, q, ctx->d_dinv, s0,
+                               red, sl.d_state, l, k);
+      tem::launch_seed_update(g, r, q, rn, red, sl.d_state, l, k);
     }
-    tem::launch_shift_block(g, J, red, sl.d_state, k);
+    if (one_kernel) tem::launch_shift_block_step(g, J, red, sl.d_state, k);
+    else tem::launch_shift_block(g, J, red, sl.d_state, k);
     extra(k);
     if (k.err != hipSuccess) return k.err;
     return hipGraphInstantiate(ex, *gr, nullptr, nullptr, 0);
@@ -1292,6 +1337,8 @@ int tem_setup_grid(tem_ctx** out, int nx, int ny, int nz, const double* hx, cons
   int n_cu = 0;
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) n_cu = 0;
   g.seed_tile = tem::choose_seed_tile(g, n_cu);
+  c->seed_one_kernel = seed_one_kernel_env();
+  if (tem::seed_step_blocks(g) > tem::kReduceSlots) return fail(nullptr, TEM_EINVAL, "grid too large: more seed tiles than partial-sum slots");
   c->n3 = 3 * g.nn;
   c->nstore = tem::storage_edges(g);
   if (tem::seed_stencil_blocks(g) > tem::kReduceSlots) return fail(nullptr, TEM_EINVAL, "grid too large: more stencil tiles than partial-sum slots");

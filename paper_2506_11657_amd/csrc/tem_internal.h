@@ -146,6 +146,18 @@ void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold,
                          hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_seed_update(const GridArgs& g, const double* r, const double* q, double* rnext, Reduce red,
                         SolveState* st, int local, Sink& k, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+// One-kernel seed step `local` (update of step i fused with the stencil of
+// step i + 1): reads r_i, p_i, q_i = A0 p_i, writes r_{i+1} (ring), p_{i+1},
+// q_{i+1}; p and q ping-pong by parity (read slot local & 1); partial sums in
+// two sets of 4 kReduceSlots entries (red.partials must hold 8 kReduceSlots).
+// first != 0: the prologue p_0 = r_0, q_0 = A0 r_0 (pass p = q = r; writes
+// slot 0 of p and q).
+void launch_seed_step(const GridArgs& g, const double* r, const double* p, const double* q, double* rn, double* pn,
+                      double* qn, const double* dinv, double s0, Reduce red, SolveState* st, int local, int first,
+                      Sink& k, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+int seed_step_blocks(const GridArgs& g);
+// the shift recurrences after a block of one-kernel seed steps (history complete)
+void launch_shift_block_step(const GridArgs& g, int J, Reduce red, SolveState* st, Sink& k, int f = 0);
 // R: the block's ring part (slot l holds r_{k0+l}, l = 1 .. B-1), R0: the slot
 // holding r_{k0+B}; coefficient set f
 void launch_block_update(const GridArgs& g, const double* R, const double* R0, double2* Y, double2* P, int J, int B,

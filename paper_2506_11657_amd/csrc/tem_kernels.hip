@@ -294,14 +294,6 @@ __device__ void stencil_tile(const GridArgs& g, const double* __restrict__ dinv,
 }
 
 // ---------------------------------------------------------------------------
-// Real stencil block, all planes at once: a block owns TX x TY node columns
-// and KZ planes; it loads the scaled field of planes k0-1 .. k0+KZ (one-node
-// halo in x and y) into LDS in a single burst of independent loads, computes
-// the face fluxes of planes k0-1 .. k0+KZ-1, then the three edges of each
-// owned node.  The owner's own unscaled values and dinv are loaded into
-// registers in the same burst.
-// own(c, kz) -> (u, d) is supplied through load(v, c) and dinv.
-// ---------------------------------------------------------------------------
 // Block-3-D stencil tile: all KZ + 2 node planes of a TX x TY tile plus a
 // one-node halo are staged at once.  The raw inputs of every staged value are
 // fetched into registers first (fetch(v, c) returns them); the caller's pre()
@@ -309,15 +301,22 @@ __device__ void stencil_tile(const GridArgs& g, const double* __restrict__ dinv,
 // previous kernel's partials that yields the recurrence scalars); finally
 // combine(raw) forms the value, which is scaled by M^-1/2 into LDS.  The face
 // fluxes of KZ + 1 planes are formed in LDS from the 1-D width products, and
-// emit(v, c, (K p')_c, u, M^-1/2) receives every owned edge.
+// emit(v, c, (K p')_c, raw, M^-1/2) receives every owned edge.
+//
+// Staging order: thread (tx, ty) fetches its own node column (i, j) through
+// all KZ + 2 planes, which holds its owned nodes, so their raw values and
+// M^-1/2 stay in registers for emit with no second load; each row of a
+// plane is one contiguous 64-entry wave access.  The border ring of the
+// tile (2 (TX + 2) + 2 TY entries per plane) is spread over all threads.
+// ---------------------------------------------------------------------------
 template <int TX, int TY, int KZ, typename FetchFn, typename PreFn, typename CombineFn, typename EmitFn>
 __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ dinv, int bx, int by, int zb, FetchFn fetch, PreFn pre,
                                 CombineFn combine, EmitFn emit) {
   constexpr int NP = KZ + 2;                                // planes loaded
-  constexpr int NE = (TX + 2) * (TY + 2);                   // entries per plane
   constexpr int NT = TX * TY;
   constexpr int NF = (TX + 1) * (TY + 1);                   // flux entries per plane
-  constexpr int NL = (NP * NE + NT - 1) / NT;               // staged entries per thread
+  constexpr int NB = 2 * (TX + 2) + 2 * TY;                 // border entries per plane
+  constexpr int NBL = (NP * NB + NT - 1) / NT;              // border entries per thread
   using Raw = decltype(fetch(0LL, 0));
   __shared__ double sp[NP][3][TY + 2][TX + 2];
   __shared__ double phi[KZ + 1][3][TY + 1][TX + 1];
@@ -331,34 +330,49 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
   const int k0 = zb * KZ;
   const int i = i0 + tx, j = j0 + ty;
   const bool own = (i < g.nx) && (j < g.ny);
-  // 1. issue every load: own raw values, staged raw values and M^-1/2, weights
-  Raw ou[KZ][3];
-  double od[KZ][3];
+  // 1. issue every load: the thread's column (planes k0-1 .. k0+KZ), its
+  // share of the border ring, the weights
+  Raw cr[NP][3];
+  double cd[NP][3];
+  const bool col = i < g.px && j < g.py;
 #pragma unroll
-  for (int z = 0; z < KZ; ++z) {
-    const int kk = k0 + z;
-    const bool ok = own && kk < g.nz;
-    const long long v = ok ? node_of(g, i, j, kk) : 0;
+  for (int pl = 0; pl < NP; ++pl) {
+    const int kk = k0 - 1 + pl;
+    const bool in = col && kk >= 0 && kk < g.pz;
+    const long long v = in ? node_of(g, i, j, kk) : 0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      od[z][c] = ok ? dinv[c * g.nn + v] : 0.0;
-      ou[z][c] = ok ? fetch(v, c) : Raw{};
+      cd[pl][c] = in ? dinv[c * g.nn + v] : 0.0;
+      cr[pl][c] = in ? fetch(v, c) : Raw{};
     }
   }
-  Raw hr[NL][3];
-  double hd[NL][3];
+  Raw br[NBL][3];
+  double bd[NBL][3];
+  int bpos[NBL];  // (plane, row, column) of the border entry packed as pl * (TY + 2) * (TX + 2) + lj * (TX + 2) + li
 #pragma unroll
-  for (int l = 0; l < NL; ++l) {
-    const int e = tid + l * NT;
-    const int pl = e / NE, r = e % NE;
-    const int li = r % (TX + 2), lj = r / (TX + 2);
+  for (int m = 0; m < NBL; ++m) {
+    const int b = tid + m * NT;
+    const int pl = b / NB, rb = b % NB;
+    int li, lj;
+    if (rb < TX + 2) {  // the low row
+      li = rb;
+      lj = 0;
+    } else if (rb < 2 * (TX + 2)) {  // the high row
+      li = rb - (TX + 2);
+      lj = TY + 1;
+    } else {  // the low and high column of the rows in between
+      const int rr = rb - 2 * (TX + 2);
+      lj = 1 + (rr >> 1);
+      li = (rr & 1) ? TX + 1 : 0;
+    }
+    bpos[m] = (pl * (TY + 2) + lj) * (TX + 2) + li;
     const int gi = i0 - 1 + li, gj = j0 - 1 + lj, kk = k0 - 1 + pl;
-    const bool in = e < NP * NE && gi >= 0 && gi < g.px && gj >= 0 && gj < g.py && kk >= 0 && kk < g.pz;
+    const bool in = b < NP * NB && gi >= 0 && gi < g.px && gj >= 0 && gj < g.py && kk >= 0 && kk < g.pz;
     const long long v = in ? node_of(g, gi, gj, kk) : 0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      hd[l][c] = in ? dinv[c * g.nn + v] : 0.0;
-      hr[l][c] = in ? fetch(v, c) : Raw{};
+      bd[m][c] = in ? dinv[c * g.nn + v] : 0.0;
+      br[m][c] = in ? fetch(v, c) : Raw{};
     }
   }
   // 1-D weights of the block's flux nodes: entries (TX + 1) + (TY + 1) + (KZ + 1),
@@ -409,15 +423,17 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
   }
   // 3. staged values into LDS
 #pragma unroll
-  for (int l = 0; l < NL; ++l) {
-    const int e = tid + l * NT;
-    if (e < NP * NE) {
-      const int pl = e / NE, r = e % NE;
-      const int li = r % (TX + 2), lj = r / (TX + 2);
+  for (int pl = 0; pl < NP; ++pl)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) sp[pl][c][lj][li] = hd[l][c] * combine(hr[l][c]);
+    for (int c = 0; c < 3; ++c) sp[pl][c][ty + 1][tx + 1] = cd[pl][c] * combine(cr[pl][c]);
+#pragma unroll
+  for (int m = 0; m < NBL; ++m)
+    if (tid + m * NT < NP * NB) {
+      const int pos = bpos[m];
+      const int li = pos % (TX + 2), lj = (pos / (TX + 2)) % (TY + 2), pl = pos / ((TX + 2) * (TY + 2));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sp[pl][c][lj][li] = bd[m][c] * combine(br[m][c]);
     }
-  }
   __syncthreads();
   // fluxes of planes k0-1 .. k0+KZ-1 (plane index pl: kk = k0 - 1 + pl)
   for (int e = tid; e < (KZ + 1) * NF; e += NT) {
@@ -446,15 +462,15 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
   for (int z = 0; z < KZ; ++z) {
     const int kk = k0 + z;
     if (kk >= g.nz) break;
-    const int p = z + 1;  // flux plane of kk
+    const int p = z + 1;  // flux plane of kk, and its column plane
     const double fx = phi[p][0][lj][li], fy = phi[p][1][lj][li], fz = phi[p][2][lj][li];
     const double kpx = ohx * (phi[p - 1][1][lj][li] - fy + fz - phi[p][2][lj - 1][li]);
     const double kpy = ohy * (phi[p][2][lj][li - 1] - fz + fx - phi[p - 1][0][lj][li]);
     const double kpz = ohz[z] * (phi[p][0][lj - 1][li] - fx + fy - phi[p][1][lj][li - 1]);
     const long long v = node_of(g, i, j, kk);
-    emit(v, 0, kpx, ou[z][0], od[z][0]);
-    emit(v, 1, kpy, ou[z][1], od[z][1]);
-    emit(v, 2, kpz, ou[z][2], od[z][2]);
+    emit(v, 0, kpx, cr[p][0], cd[p][0]);
+    emit(v, 1, kpy, cr[p][1], cd[p][1]);
+    emit(v, 2, kpz, cr[p][2], cd[p][2]);
   }
 }
 
@@ -563,6 +579,164 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(TX 
                                      blockIdx.y, blockIdx.z, bid);
 }
 
+// ---------------------------------------------------------------------------
+// Seed CG in one kernel per iteration: the update of step i fused with the
+// stencil of step i + 1, with one reduction point between kernels.  Kernel
+// `local` (step i = k0 + local of the block starting at k0) reads r_i, p_i and
+// q_i = A0 p_i and the partial sums of four inner products of step i, then
+//   alpha_i = (r_i, r_i) / (p_i, q_i)
+//   (r_{i+1}, r_{i+1}) ~ (r_i, r_i) - 2 alpha_i (r_i, q_i) + alpha_i^2 (q_i, q_i)
+//   beta_i = that / (r_i, r_i)
+//   r_{i+1} = r_i - alpha_i q_i,  p_{i+1} = r_{i+1} + beta_i p_i,  q_{i+1} = A0 p_{i+1}
+// and leaves the partials of (r_{i+1}, r_{i+1}), (p_{i+1}, q_{i+1}),
+// (r_{i+1}, q_{i+1}), (q_{i+1}, q_{i+1}).  r_{i+1} and p_{i+1} are formed on
+// the tile's halo from r_i, q_i and p_i (three loads per staged entry).
+// As in the two-kernel form, q = A0 p is applied to the search direction
+// itself, so the residual recurrence carries no rounding amplified by ||A0||
+// (the arrangement of Chronopoulos and Gear, which applies A0 to r and keeps
+// A0 p by a second recurrence, lost two orders of attainable accuracy on
+// these systems); alpha always divides the inner product of the stored
+// residual, and only beta uses the one-step expansion, whose cancellation is
+// bounded by the residual's reduction in one step.  The recorded history
+// (alpha_k, beta_k, (r_{k+1}, r_{k+1}) of the block's steps) and the ring
+// (r_{k0+l} in slot l) are those of the two-kernel form, and the history is
+// complete after the block's last kernel.
+// Buffers ping-pong by parity: kernel `local` reads p, q and partial set
+// local & 1 and writes set (local + 1) & 1; set m of the partials holds the
+// four inner products at parts + (4 m + v) NS, NS = kReduceSlots.
+// With first != 0 the kernel is the prologue of the solve: alpha = beta = 0
+// (pass p = q = r), so it forms p_0 = r_0, q_0 = A0 r_0 and the partials of
+// step 0 into set 0, and writes no state and no residual.
+template <int NT>
+__device__ __forceinline__ void block_total4_n(double v[4], double (*lds)[(NT + kWave - 1) / kWave], int tid) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+    for (int off = kWave / 2; off > 0; off >>= 1) v[m] += __shfl_down(v[m], off, kWave);
+  const int lane = tid % kWave, wid = tid / kWave;
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) lds[m][wid] = v[m];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    double t = 0.0;
+    for (int w = 0; w < (NT + kWave - 1) / kWave; ++w) t += lds[m][w];
+    v[m] = t;
+  }
+}
+
+template <int TX, int TY, int KZ>
+__device__ __forceinline__ void seed_step_tile(const GridArgs& g, const double* __restrict__ r,
+                                               const double* __restrict__ p, const double* __restrict__ q,
+                                               double* __restrict__ rn, double* __restrict__ pn,
+                                               double* __restrict__ qn, const double* __restrict__ dinv, double s0,
+                                               const double* __restrict__ pin, double* __restrict__ pout, int nparts,
+                                               SolveState* st, int local, int first, int bx, int by, int bz,
+                                               int bid) {
+  constexpr int NT = TX * TY;
+  constexpr int NW = (NT + kWave - 1) / kWave;
+  constexpr int MP = 2;  // partials per thread and product requested ahead of the stencil's loads
+  __shared__ double red[4][NW];
+  const int tid = threadIdx.x + TX * threadIdx.y;
+  double pf[4][MP];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int m = 0; m < MP; ++m) pf[v][m] = pin[v * kReduceSlots + min(tid + m * NT, nparts - 1)];
+  const int B = st->B;
+  const double carry_a = st->alpha_h[B - 1], carry_b = st->beta_h[B - 1];
+  const double rr_sentinel = st->rrk[1];
+  double alpha = 0.0, beta = 0.0;
+  auto pre = [&]() {
+    double t[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      t[v] = 0.0;
+#pragma unroll
+      for (int m = 0; m < MP; ++m)
+        if (tid + m * NT < nparts) t[v] += pf[v][m];
+      for (int ix = tid + MP * NT; ix < nparts; ix += NT) t[v] += pin[v * kReduceSlots + ix];
+    }
+    block_total4_n<NT>(t, red, tid);
+    if (first) return;
+    const double rr = t[0], pq = t[1], rq = t[2], qq = t[3];
+    const bool ok = pq > 0.0 && isfinite(pq);
+    alpha = ok ? rr / pq : 0.0;
+    const double rr_next = rr - 2.0 * alpha * rq + alpha * alpha * qq;
+    const bool ok2 = rr_next >= 0.0 && isfinite(rr_next);
+    beta = ok2 ? rr_next / rr : 0.0;
+    if (bid == 0 && tid == 0) {
+      if (isinf(rr_sentinel)) {  // first step: rr_0 = (g, g) scales the stopping tolerance
+        st->rr0 = rr;
+        st->tol2 *= rr;
+        st->rrk[1] = rr;
+      }
+      if (local == 0) {  // alpha, beta of the step before this block, for the shift recurrences
+        st->carry_alpha = carry_a;
+        st->carry_beta = carry_b;
+      }
+      st->alpha_h[local] = alpha;
+      st->beta_h[local] = beta;
+      st->rr_h[local] = rr_next;
+      st->pAp = pq;
+      if (!isfinite(rr) || !ok || !ok2) st->breakdown = 1;
+    }
+  };
+  struct RPQ {
+    double r, p, q;
+  };
+  auto fetch = [&](long long v, int c) {
+    const long long e = c * g.nn + v;
+    return RPQ{r[e], p[e], q[e]};
+  };
+  auto rnext = [&](const RPQ& x) { return x.r - alpha * x.q; };
+  auto combine = [&](const RPQ& x) { return rnext(x) + beta * x.p; };
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  auto emit = [&](long long v, int c, double kp, const RPQ& x, double d) {
+    const long long e = c * g.nn + v;
+    const double rv = rnext(x);
+    const double pv = combine(x);
+    const double qv = d * kp + s0 * pv;
+    if (!first) rn[e] = rv;
+    pn[e] = pv;
+    qn[e] = qv;
+    acc[0] += rv * rv;
+    acc[1] += pv * qv;
+    acc[2] += rv * qv;
+    acc[3] += qv * qv;
+  };
+  stencil_block3d<TX, TY, KZ>(g, dinv, bx, by, bz, fetch, pre, combine, emit);
+  // fixed-order block sums of the four products
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+    for (int off = kWave / 2; off > 0; off >>= 1) acc[m] += __shfl_down(acc[m], off, kWave);
+  const int lane = tid % kWave, wid = tid / kWave;
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) red[m][wid] = acc[m];
+  __syncthreads();
+  if (tid < 4) {
+    double t = 0.0;
+    for (int w = 0; w < NW; ++w) t += red[tid][w];
+    pout[tid * kReduceSlots + bid] = t;
+  }
+}
+
+// three staged vectors need more than the 128 VGPRs of 4 waves per SIMD
+template <int TX, int TY, int KZ>
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2)))
+k_seed_step(GridArgs g, const double* __restrict__ r, const double* __restrict__ p, const double* __restrict__ q,
+            double* __restrict__ rn, double* __restrict__ pn, double* __restrict__ qn, const double* __restrict__ dinv,
+            double s0, const double* __restrict__ pin, double* __restrict__ pout, SolveState* st, int local,
+            int first) {
+  const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const int nparts = gridDim.x * gridDim.y * gridDim.z;
+  seed_step_tile<TX, TY, KZ>(g, r, p, q, rn, pn, qn, dinv, s0, pin, pout, nparts, st, local, first, blockIdx.x,
+                             blockIdx.y, blockIdx.z, bid);
+}
+
 // Block blk of the nblk blocks of one seed update (grid-stride over the n entries).
 __device__ __forceinline__ void seed_update_block(long long n, const double* __restrict__ r,
                                                   const double* __restrict__ q, double* __restrict__ rnext,
@@ -636,27 +810,34 @@ __global__ void __launch_bounds__(UPD_T) k_seed_update(long long n, const double
 //   alpha^s_k = a_k zeta_{k+1}/zeta_k,  beta^s_k = b_k (zeta_{k+1}/zeta_k)^2,
 //   y_{k+1} = y_k + alpha^s_k p_k,  p_{k+1} = zeta_{k+1} r_{k+1} + beta^s_k p_k,
 // accumulated as coefficients of the block's starting p and residuals r_l.
-__device__ __forceinline__ void shift_block_wave(const double* __restrict__ upd_partials, SolveState* st, int j,
+// rr_partials: the n partial sums of (r_{k+1}, r_{k+1}) the block's last seed
+// update left, from which the block's last beta_k and (r_{k+1}, r_{k+1}) are
+// completed here; n = 0: the seed kernels recorded the whole history.
+__device__ __forceinline__ void shift_block_wave(const double* __restrict__ rr_partials, int n, SolveState* st, int j,
                                                  int f) {
   const int lane = threadIdx.x;
-  constexpr int NPART = (UPD_BLOCKS + kWave - 1) / kWave;
+  constexpr int NPART = 32;  // partials prefetched per lane (n <= 2048 in one round trip)
   __shared__ double red[1];
-  // the update's partials and the state's scalars are all requested before
-  // any is used (one round trip instead of several in sequence)
+  // the partials and the state's scalars are all requested before any is
+  // used (one round trip instead of several in sequence)
   double part[NPART];
 #pragma unroll
-  for (int m = 0; m < NPART; ++m) part[m] = upd_partials[min(lane + m * kWave, UPD_BLOCKS - 1)];
+  for (int m = 0; m < NPART; ++m) part[m] = n > 0 ? rr_partials[min(lane + m * kWave, n - 1)] : 0.0;
   const int B = st->B;
   const int is_active = st->active[j];
-  // the block's last step: (r_{k+1}, r_{k+1}) from the update's partials, beta_k
-  double sp = part[0];
+  // the block's last step: (r_{k+1}, r_{k+1}) from the partials, beta_k
+  double sp = 0.0;
 #pragma unroll
-  for (int m = 1; m < NPART; ++m) sp += lane + m * kWave < UPD_BLOCKS ? part[m] : 0.0;
-  const double rr_last = block_total_n<kWave>(sp, red, lane);
-  const double beta_last = rr_last / st->rrk[(B - 1) & 1];
+  for (int m = 0; m < NPART; ++m) sp += lane + m * kWave < n ? part[m] : 0.0;
+  for (int m = lane + NPART * kWave; m < n; m += kWave) sp += rr_partials[m];
+  const double rr_sum = block_total_n<kWave>(sp, red, lane);
+  const double rr_last = n > 0 ? rr_sum : st->rr_h[B - 1];
+  const double beta_last = n > 0 ? rr_last / st->rrk[(B - 1) & 1] : st->beta_h[B - 1];
   if (j == 0 && lane == 0) {
-    st->beta_h[B - 1] = beta_last;
-    st->rr_h[B - 1] = rr_last;
+    if (n > 0) {
+      st->beta_h[B - 1] = beta_last;
+      st->rr_h[B - 1] = rr_last;
+    }
     st->k += B;
   }
   if (!is_active) {
@@ -736,8 +917,9 @@ __device__ __forceinline__ void shift_block_wave(const double* __restrict__ upd_
   }
 }
 
-__global__ void __launch_bounds__(64) k_shift_block(const double* __restrict__ upd_partials, SolveState* st, int f) {
-  shift_block_wave(upd_partials, st, blockIdx.x, f);
+__global__ void __launch_bounds__(64) k_shift_block(const double* __restrict__ rr_partials, int n, SolveState* st,
+                                                    int f) {
+  shift_block_wave(rr_partials, n, st, blockIdx.x, f);
 }
 
 // Deferred shift update after a block of BB seed iterations:
@@ -824,7 +1006,7 @@ __global__ void __launch_bounds__(UPD_T) k_seed_update_batch(const BatchJob* __r
 __global__ void __launch_bounds__(64) k_shift_block_batch(const BatchJob* __restrict__ jobs) {
   const BatchJob& jb = jobs[blockIdx.y];
   if ((int)blockIdx.x >= jb.J) return;
-  shift_block_wave(jb.part_up, jb.st, blockIdx.x, 0);
+  shift_block_wave(jb.part_up, UPD_BLOCKS, jb.st, blockIdx.x, 0);
 }
 
 template <int BB>
@@ -1735,6 +1917,42 @@ void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold,
 #undef TEM_SEED_CASE
 }
 
+// The one-kernel seed step uses the two-plane tile where the grid's tile
+// choice is the two-plane one, else the one-plane tile.
+static dim3 seed_step_grid(const GridArgs& g, bool* two_plane) {
+  *two_plane = pick_seed_tile(g) == 20;
+  const int kz = *two_plane ? 2 : 1;
+  return dim3((g.nx + 63) / 64, (g.ny + 7) / 8, (g.nz + kz - 1) / kz);
+}
+
+int seed_step_blocks(const GridArgs& g) {
+  bool two;
+  const dim3 d = seed_step_grid(g, &two);
+  return d.x * d.y * d.z;
+}
+
+void launch_seed_step(const GridArgs& g, const double* r, const double* p, const double* q, double* rn, double* pn,
+                      double* qn, const double* dinv, double s0, Reduce red, SolveState* st, int local, int first,
+                      Sink& k, hipEvent_t t0, hipEvent_t t1) {
+  bool two;
+  const dim3 grid = seed_step_grid(g, &two), block(64, 8);
+  const int in = first ? 1 : (local & 1);  // the prologue reads an unused set
+  const double* pin = red.partials + (size_t)in * 4 * kReduceSlots;
+  double* pout = red.partials + (size_t)(1 - in) * 4 * kReduceSlots;
+  if (first) pout = red.partials;  // step 0's partials: set 0
+  if (two)
+    put(k, k_seed_step<64, 8, 2>, grid, block, 0u, t0, t1, g, r, p, q, rn, pn, qn, dinv, s0, pin, pout, st, local,
+        first);
+  else
+    put(k, k_seed_step<64, 8, 1>, grid, block, 0u, t0, t1, g, r, p, q, rn, pn, qn, dinv, s0, pin, pout, st, local,
+        first);
+}
+
+void launch_shift_block_step(const GridArgs& g, int J, Reduce red, SolveState* st, Sink& k, int f) {
+  (void)g;
+  put(k, k_shift_block, dim3(J), dim3(64), 0u, nullptr, nullptr, (const double*)red.partials, 0, st, f);
+}
+
 void launch_seed_update(const GridArgs& g, const double* r, const double* q, double* rnext, Reduce red,
                         SolveState* st, int local, Sink& k, hipEvent_t t0, hipEvent_t t1) {
   const long long n3 = 3 * g.nn;
@@ -1751,7 +1969,8 @@ int seed_stencil_blocks(const GridArgs& g) {
 
 void launch_shift_block(const GridArgs& g, int J, Reduce red, SolveState* st, Sink& k, int f) {
   (void)g;
-  put(k, k_shift_block, dim3(J), dim3(64), 0u, nullptr, nullptr, (const double*)(red.partials + kReduceSlots), st, f);
+  put(k, k_shift_block, dim3(J), dim3(64), 0u, nullptr, nullptr, (const double*)(red.partials + kReduceSlots),
+      UPD_BLOCKS, st, f);
 }
 
 void launch_seed_stencil_batch(const BatchJob* jobs, int njobs, int total_tiles, int B, int local, Sink& k) {

@@ -145,17 +145,23 @@ def test_forward_parity_ragged_tiles_two_sources(tem):
         assert pinned.sum() >= 5 and np.all(eu[pinned] <= 1e-8 * un[pinned])
 
 
+@pytest.mark.parametrize("seed", ["cg", "hs"])
 @pytest.mark.parametrize("tile", ["17", "20"])
-def test_stencil_tiles_parity_ragged(tem, tile, monkeypatch):
+def test_stencil_tiles_parity_ragged(tem, tile, seed, monkeypatch):
     """Both stencil tiles the library chooses between, the one-plane (64, 8, 1)
     and the two-plane (64, 8, 2), on a grid with ragged tails in x, y and an
-    odd nz (a two-plane tile holds one plane): every shift matches the direct
-    solve (TEM_SEED_TILE fixes the tile for contexts created while it is set)."""
+    odd nz (a two-plane tile holds one plane), with both forms of the seed
+    iteration (one kernel per iteration, the default, and the two-kernel
+    stencil + update form): every shift matches the direct solve
+    (TEM_SEED_TILE and TEM_SEED fix the tile and the form for contexts created
+    while they are set)."""
     monkeypatch.setenv("TEM_SEED_TILE", tile)
+    monkeypatch.setenv("TEM_SEED", seed)
     wl = W.ragged70()
     ctx, stats, res = _parity(tem, wl, 16, method="banded")
     ex, eu, un, Sk, ed, dn, Sd = res[0]
-    print("tile %s: iterations %d, max shift err %.2e" % (tile, stats["iterations"], ex.max()))
+    print("tile %s, seed %s: iterations %d, max shift err %.2e, max true residual %.2e"
+          % (tile, seed, stats["iterations"], ex.max(), max(stats["true_res"])))
     assert stats["converged"] and ex.max() <= 1e-9
     assert np.all(eu <= 1e-8 * un + 1e-9 * Sk)
     assert np.all(ed <= 1e-8 * dn + 1e-9 * Sd)
