@@ -199,7 +199,10 @@ def adjoint_bench(args):
     if args.load_grad:
         z = np.load(args.load_grad)
         g, d = z["g"], z["d"]
-        assert np.array_equal(z["d_obs"], d_obs), "stored gradient belongs to other data"
+        # the same workload: equal to the solvers' rounding (the stored run may have used another seed form)
+        dev = float(np.abs(z["d_obs"] - d_obs).max() / np.abs(d_obs).max())
+        print("stored observed data deviate by %.1e of max |d_obs|" % dev, file=sys.stderr, flush=True)
+        assert dev <= 1e-6, "stored gradient belongs to other data"
         timing = {k: float(z[k]) for k in ("forward_s", "adjoint_s", "unknown_updates") if k in z}
         sa_iters = None
     else:

@@ -129,7 +129,7 @@ struct tem_ctx {
   DevBuf refine64, refdot;             // precision 1: FP64 corrections d_j and (A + s_j) d_j; step lengths
   std::vector<DevBuf> Y;  // per source (kept) or one
   // stored forward state for the adjoint
-  bool seed_one_kernel = true;  // seed CG in one kernel per iteration (else stencil + update)
+  bool seed_one_kernel = true;  // seed CG form (seed_one_kernel_for)
   bool fwd_meta = false;   // the last forward's sources, receivers, poles and options are recorded
   bool fwd_valid = false;  // ... and its solutions are kept on the device
   int fwd_J = 0, fwd_T = 0, fwd_nsrc = 0, fwd_nrx = 0;
@@ -168,12 +168,21 @@ int overlap_blocks() {
 }
 
 // Seed CG form of a context's solves, fixed when the context is created: one
-// kernel per iteration (update fused with the next stencil, the default) or
-// the two-kernel stencil + update form (TEM_SEED=hs).  The batched engine uses
-// the two-kernel form.
-bool seed_one_kernel_env() {
+// kernel per iteration (the update fused with the next stencil, on unscaled
+// vectors M^-1/2 v) when its tiles fit on the device's compute units in one
+// round, else the two-kernel stencil + update form.  With one tile per CU
+// the iteration is a chain of latencies and one kernel saves a launch and a
+// round trip (64^3: 5.14 s against 5.60 s per model); with several rounds
+// of tiles the two-plane tile's 2 waves per SIMD hide less than the
+// two-kernel form's stencil at 4 waves per SIMD plus a streaming update
+// (128^3: 169 us against 148 us per iteration).  TEM_SEED=hs or =one forces
+// a form.  The batched engine, whose jobs fill the device together, uses the
+// two-kernel form.
+bool seed_one_kernel_for(const GridArgs& g, int n_cu) {
   const char* e = getenv("TEM_SEED");
-  return !(e && e[0] == 'h' && e[1] == 's');
+  if (e && !strcmp(e, "hs")) return false;
+  if (e && !strcmp(e, "one")) return true;
+  return n_cu > 0 && tem::seed_step_blocks(g) <= n_cu;
 }
 
 // TEM_VERBOSE=1: progress lines on stderr from long solves
@@ -719,6 +728,7 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
   // the block's own launch sequence.
   const bool overlap = overlap_updates();
   const bool one_kernel = ctx->seed_one_kernel;
+  const bool unscaled = one_kernel;  // the one-kernel form's ring holds M^-1/2 r
   const int RS = overlap ? tem::kPhases * B : B;  // ring slots
   // pbuf: p_{k-1}, p_k by parity (two-kernel form), or p_i, p_{i+1} and then
   // q_i, q_{i+1} by parity (one-kernel form)
@@ -749,7 +759,8 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     if (one_kernel) tem::launch_shift_block_step(g, J, red, sl.d_state, st, f);
     else tem::launch_shift_block(g, J, red, sl.d_state, st, f);
     if (!overlap) {
-      tem::launch_block_update(g, R, R, Ys[i], (PV*)sl.P.p, J, B, sl.d_state, st, 0);
+      tem::launch_block_update(g, R, R, Ys[i], (PV*)sl.P.p, J, B, sl.d_state, st, 0, 4096,
+                               unscaled ? ctx->d_sqrtm : nullptr);
       if (timed) (void)hipEventRecord(ev[4 * B + 1], st.stream);
     }
   };
@@ -764,7 +775,7 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     tem::Sink d;
     d.stream = sl.stream2;
     tem::launch_block_update(g, R + (size_t)f * B * n3, R + (size_t)((f + 1) % tem::kPhases) * B * n3, Ys[i],
-                             (PV*)sl.P.p, J, B, sl.d_state, d, f, overlap_blocks());
+                             (PV*)sl.P.p, J, B, sl.d_state, d, f, overlap_blocks(), unscaled ? ctx->d_sqrtm : nullptr);
     if (timed) (void)hipEventRecord(ev[4 * B + 1], sl.stream2);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipEventRecord(sl.bu_ev[f], sl.stream2);
@@ -809,7 +820,7 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
     if (se == hipSuccess) {
       const tem::Reduce red{(double*)sl.partials.p, ctx->d_counters};
       tem::launch_seed_init(g, (const double*)sl.gvec.p, (double*)sl.R.p, (double*)sl.pbuf.p + n3, Ys[i],
-                            (PV*)sl.P.p, J, red, sl.d_state, st);
+                            (PV*)sl.P.p, J, red, sl.d_state, st, unscaled ? ctx->d_dinv : nullptr);
       if (one_kernel) {  // p_0 = r_0, q_0 = A0 r_0 into slot 0 and the partials of step 0
         tem::Sink pro;
         pro.stream = st;
@@ -1076,6 +1087,7 @@ int lanczos_source(tem_ctx* ctx, int i, const std::vector<double>& shifts_re, co
   int rc;
   SolveSlot& sl = ctx->slots[i];
   const bool one_kernel = ctx->seed_one_kernel;
+  const bool unscaled = one_kernel;  // the one-kernel form's ring holds M^-1/2 r
   if ((rc = ensure(ctx, sl.R, (size_t)B * n3 * sizeof(double))) ||
       (rc = ensure(ctx, sl.pbuf, (one_kernel ? 4 : 2) * n3 * sizeof(double))) ||
       (rc = ensure(ctx, sl.q, n3 * sizeof(double))) ||
@@ -1122,7 +1134,7 @@ int lanczos_source(tem_ctx* ctx, int i, const std::vector<double>& shifts_re, co
     hipError_t e = hipMemcpyAsync(sl.d_state, hs.get(), sizeof(SolveState), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
     tem::launch_seed_init(g, (const double*)sl.gvec.p, R, pb + n3, (double2*)nullptr, (double2*)nullptr, 0, red,
-                          sl.d_state, st);
+                          sl.d_state, st, unscaled ? ctx->d_dinv : nullptr);
     if (one_kernel) {
       tem::Sink pro;
       pro.stream = st;
@@ -1171,14 +1183,15 @@ int lanczos_source(tem_ctx* ctx, int i, const std::vector<double>& shifts_re, co
   if (e == hipSuccess && n_rx > 0) {
     tem::Sink d;
     d.stream = st;
-    tem::launch_ring_receivers(g, R, B, ctx->d_dinv, rxp, n_rx, ctx->ks, (double*)hqd.p, 1, d);
+    tem::launch_ring_receivers(g, R, B, unscaled ? nullptr : ctx->d_dinv, rxp, n_rx, ctx->ks, (double*)hqd.p, 1, d);
     hq.resize(n_rx);
     e = hipMemcpyAsync(hq.data(), hqd.p, n_rx * sizeof(double), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
   }
   if (e == hipSuccess)
     e = build(&g1, &x1, [&](tem::Sink& k) {
-      if (n_rx > 0) tem::launch_ring_receivers(g, R, B, ctx->d_dinv, rxp, n_rx, ctx->ks, (double*)hqd.p, 0, k);
+      if (n_rx > 0)
+        tem::launch_ring_receivers(g, R, B, unscaled ? nullptr : ctx->d_dinv, rxp, n_rx, ctx->ks, (double*)hqd.p, 0, k);
     });
   int launched = 0, checked = 0;
   bool done = false, breakdown = false;
@@ -1284,7 +1297,8 @@ int lanczos_source(tem_ctx* ctx, int i, const std::vector<double>& shifts_re, co
       });
     for (int b = 0; b < nblk && e == hipSuccess; ++b) e = hipGraphLaunch(x2, st);
     if (e == hipSuccess) {
-      tem::launch_ring_fields(g, (const double*)Ud.p, T, ctx->d_dinv, fields, rxp, 0, ctx->ks, nullptr, st);
+      tem::launch_ring_fields(g, (const double*)Ud.p, T, unscaled ? nullptr : ctx->d_dinv, fields, rxp, 0, ctx->ks,
+                              nullptr, st);
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -1337,7 +1351,11 @@ int tem_setup_grid(tem_ctx** out, int nx, int ny, int nz, const double* hx, cons
   int n_cu = 0;
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) n_cu = 0;
   g.seed_tile = tem::choose_seed_tile(g, n_cu);
-  c->seed_one_kernel = seed_one_kernel_env();
+  {  // TEM_SEED_TILE=17 (the one-plane stencil tile) also gives the one-kernel step one plane per tile
+    const char* e = getenv("TEM_SEED_TILE");
+    g.step_kz = (e && atoi(e) == 17) ? 1 : 2;
+  }
+  c->seed_one_kernel = seed_one_kernel_for(g, n_cu);
   if (tem::seed_step_blocks(g) > tem::kReduceSlots) return fail(nullptr, TEM_EINVAL, "grid too large: more seed tiles than partial-sum slots");
   c->n3 = 3 * g.nn;
   c->nstore = tem::storage_edges(g);

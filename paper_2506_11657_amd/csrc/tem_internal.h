@@ -35,6 +35,7 @@ struct GridArgs {
   const double* ih[3];      // 1 / width, last entry 0
   const double* dw[3];      // dual width / mu0 per node, length n_a + 1
   int seed_tile = -1;       // seed stencil tile shape (index into the launcher table; host side)
+  int step_kz = 2;          // planes per tile of the one-kernel seed step (64 x 8 columns; host side)
 };
 
 // Seed-recurrence scalars and per-shift state; lives in device memory.  The
@@ -136,10 +137,11 @@ void launch_scale(long long n, const double* a, const double* x, double* y, hipS
 void launch_to_complex(long long n, const double* x, double2* y, hipStream_t s);
 void launch_zero2(long long n, double2* y, hipStream_t s);
 void launch_store2(double* p, double a, double b, hipStream_t s);
+// r0 = gvec, or r0_scale * gvec (the unscaled seed form's ring)
 void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, double2* Y, double2* P,
-                      int J, Reduce red, SolveState* st, hipStream_t s);
+                      int J, Reduce red, SolveState* st, hipStream_t s, const double* r0_scale = nullptr);
 void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, double2* Y, float2* P,
-                      int J, Reduce red, SolveState* st, hipStream_t s);
+                      int J, Reduce red, SolveState* st, hipStream_t s, const double* r0_scale = nullptr);
 // with t0 != nullptr the dispatch records its own start (t0) and stop (t1) events
 void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold, double* pnew, double* q,
                          const double* dinv, double s0, Reduce red, SolveState* st, int local, Sink& k,
@@ -151,7 +153,7 @@ void launch_seed_update(const GridArgs& g, const double* r, const double* q, dou
 // q_{i+1}; p and q ping-pong by parity (read slot local & 1); partial sums in
 // two sets of 4 kReduceSlots entries (red.partials must hold 8 kReduceSlots).
 // first != 0: the prologue p_0 = r_0, q_0 = A0 r_0 (pass p = q = r; writes
-// slot 0 of p and q).
+// slot 0 of p and q).  The vectors (and the ring) hold M^-1/2 v.
 void launch_seed_step(const GridArgs& g, const double* r, const double* p, const double* q, double* rn, double* pn,
                       double* qn, const double* dinv, double s0, Reduce red, SolveState* st, int local, int first,
                       Sink& k, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
@@ -160,11 +162,14 @@ int seed_step_blocks(const GridArgs& g);
 void launch_shift_block_step(const GridArgs& g, int J, Reduce red, SolveState* st, Sink& k, int f = 0);
 // R: the block's ring part (slot l holds r_{k0+l}, l = 1 .. B-1), R0: the slot
 // holding r_{k0+B}; coefficient set f
+// rscale != nullptr: the ring holds M^-1/2 r, scaled back by rscale = M^1/2
 void launch_block_update(const GridArgs& g, const double* R, const double* R0, double2* Y, double2* P, int J, int B,
-                         const SolveState* st, Sink& k, int f = 0, int max_blocks = 4096);
+                         const SolveState* st, Sink& k, int f = 0, int max_blocks = 4096,
+                         const double* rscale = nullptr);
 // precision 1: y_j in FP64, p_j in FP32
 void launch_block_update(const GridArgs& g, const double* R, const double* R0, double2* Y, float2* P, int J, int B,
-                         const SolveState* st, Sink& k, int f = 0, int max_blocks = 4096);
+                         const SolveState* st, Sink& k, int f = 0, int max_blocks = 4096,
+                         const double* rscale = nullptr);
 // J node-padded complex vectors, FP32 storage widened to FP64: sign 0 sets
 // Y_j = X_j for all j; sign +1 / -1 adds / subtracts X_j for the j in mask
 void launch_accumulate(const GridArgs& g, int J, const float2* X, double2* Y, int sign, unsigned long long mask,
@@ -183,6 +188,7 @@ void launch_gather_solutions(const GridArgs& g, const double2* Y, int J, const d
 void launch_scatter_storage(const GridArgs& g, const double2* xpub, const double* w, double2* xpad, hipStream_t s);
 void launch_gather_storage(const GridArgs& g, const double2* xpad, const double* w, double2* xpub, hipStream_t s);
 // two-pass form: receiver values and channel contraction straight from the seed residual ring
+// (dinv = nullptr: the ring already holds M^-1/2 r)
 void launch_ring_receivers(const GridArgs& g, const double* R, int B, const double* dinv, const int* rx, int n_rx,
                            int ks, double* hq, int init, Sink& k);
 void launch_ring_contract_init(const GridArgs& g, const double* r0, const double* W, int T, double* U, hipStream_t s);

@@ -309,7 +309,11 @@ __device__ void stencil_tile(const GridArgs& g, const double* __restrict__ dinv,
 // plane is one contiguous 64-entry wave access.  The border ring of the
 // tile (2 (TX + 2) + 2 TY entries per plane) is spread over all threads.
 // ---------------------------------------------------------------------------
-template <int TX, int TY, int KZ, typename FetchFn, typename PreFn, typename CombineFn, typename EmitFn>
+// With SCALED = false the staged values are combine(raw) itself (the caller's
+// vectors already carry the M^-1/2 scaling) and M^-1/2 is read at the owned
+// nodes only.
+template <int TX, int TY, int KZ, bool SCALED = true, typename FetchFn, typename PreFn, typename CombineFn,
+          typename EmitFn>
 __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ dinv, int bx, int by, int zb, FetchFn fetch, PreFn pre,
                                 CombineFn combine, EmitFn emit) {
   constexpr int NP = KZ + 2;                                // planes loaded
@@ -340,9 +344,11 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
     const int kk = k0 - 1 + pl;
     const bool in = col && kk >= 0 && kk < g.pz;
     const long long v = in ? node_of(g, i, j, kk) : 0;
+    const bool ownpl = pl >= 1 && pl <= KZ;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      cd[pl][c] = in ? dinv[c * g.nn + v] : 0.0;
+      if (SCALED || ownpl) cd[pl][c] = in ? dinv[c * g.nn + v] : 0.0;
+      else cd[pl][c] = 1.0;
       cr[pl][c] = in ? fetch(v, c) : Raw{};
     }
   }
@@ -371,7 +377,7 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
     const long long v = in ? node_of(g, gi, gj, kk) : 0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      bd[m][c] = in ? dinv[c * g.nn + v] : 0.0;
+      bd[m][c] = SCALED ? (in ? dinv[c * g.nn + v] : 0.0) : 1.0;
       br[m][c] = in ? fetch(v, c) : Raw{};
     }
   }
@@ -425,14 +431,15 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
 #pragma unroll
   for (int pl = 0; pl < NP; ++pl)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) sp[pl][c][ty + 1][tx + 1] = cd[pl][c] * combine(cr[pl][c]);
+    for (int c = 0; c < 3; ++c)
+      sp[pl][c][ty + 1][tx + 1] = SCALED ? cd[pl][c] * combine(cr[pl][c]) : combine(cr[pl][c]);
 #pragma unroll
   for (int m = 0; m < NBL; ++m)
     if (tid + m * NT < NP * NB) {
       const int pos = bpos[m];
       const int li = pos % (TX + 2), lj = (pos / (TX + 2)) % (TY + 2), pl = pos / ((TX + 2) * (TY + 2));
 #pragma unroll
-      for (int c = 0; c < 3; ++c) sp[pl][c][lj][li] = bd[m][c] * combine(br[m][c]);
+      for (int c = 0; c < 3; ++c) sp[pl][c][lj][li] = SCALED ? bd[m][c] * combine(br[m][c]) : combine(br[m][c]);
     }
   __syncthreads();
   // fluxes of planes k0-1 .. k0+KZ-1 (plane index pl: kk = k0 - 1 + pl)
@@ -607,6 +614,11 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(TX 
 // With first != 0 the kernel is the prologue of the solve: alpha = beta = 0
 // (pass p = q = r), so it forms p_0 = r_0, q_0 = A0 r_0 and the partials of
 // step 0 into set 0, and writes no state and no residual.
+// XS: the vectors are kept unscaled, v_x = M^-1/2 v (the Jacobi-preconditioned
+// CG on K + s0 M, the same iteration): no scaling on the halo, and at owned
+// edges q_x = M^-1 (K p_x) + s0 p_x and the inner products weighted by M
+// (1 / (M^-1/2)^2, zero on the boundary edges, where every vector is zero).
+// The ring then holds M^-1/2 r, which the block update scales back.
 template <int NT>
 __device__ __forceinline__ void block_total4_n(double v[4], double (*lds)[(NT + kWave - 1) / kWave], int tid) {
 #pragma unroll
@@ -626,7 +638,7 @@ __device__ __forceinline__ void block_total4_n(double v[4], double (*lds)[(NT + 
   }
 }
 
-template <int TX, int TY, int KZ>
+template <int TX, int TY, int KZ, bool XS>
 __device__ __forceinline__ void seed_step_tile(const GridArgs& g, const double* __restrict__ r,
                                                const double* __restrict__ p, const double* __restrict__ q,
                                                double* __restrict__ rn, double* __restrict__ pn,
@@ -697,16 +709,28 @@ __device__ __forceinline__ void seed_step_tile(const GridArgs& g, const double* 
     const long long e = c * g.nn + v;
     const double rv = rnext(x);
     const double pv = combine(x);
-    const double qv = d * kp + s0 * pv;
     if (!first) rn[e] = rv;
     pn[e] = pv;
-    qn[e] = qv;
-    acc[0] += rv * rv;
-    acc[1] += pv * qv;
-    acc[2] += rv * qv;
-    acc[3] += qv * qv;
+    if constexpr (XS) {
+      const double mi = d * d;
+      const double qv = mi * kp + s0 * pv;
+      const double m = d > 0.0 ? 1.0 / mi : 0.0;
+      const double mq = m * qv;
+      qn[e] = qv;
+      acc[0] += m * rv * rv;
+      acc[1] += pv * mq;
+      acc[2] += rv * mq;
+      acc[3] += qv * mq;
+    } else {
+      const double qv = d * kp + s0 * pv;
+      qn[e] = qv;
+      acc[0] += rv * rv;
+      acc[1] += pv * qv;
+      acc[2] += rv * qv;
+      acc[3] += qv * qv;
+    }
   };
-  stencil_block3d<TX, TY, KZ>(g, dinv, bx, by, bz, fetch, pre, combine, emit);
+  stencil_block3d<TX, TY, KZ, !XS>(g, dinv, bx, by, bz, fetch, pre, combine, emit);
   // fixed-order block sums of the four products
 #pragma unroll
   for (int m = 0; m < 4; ++m)
@@ -725,7 +749,7 @@ __device__ __forceinline__ void seed_step_tile(const GridArgs& g, const double* 
 }
 
 // three staged vectors need more than the 128 VGPRs of 4 waves per SIMD
-template <int TX, int TY, int KZ>
+template <int TX, int TY, int KZ, bool XS>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2)))
 k_seed_step(GridArgs g, const double* __restrict__ r, const double* __restrict__ p, const double* __restrict__ q,
             double* __restrict__ rn, double* __restrict__ pn, double* __restrict__ qn, const double* __restrict__ dinv,
@@ -733,8 +757,8 @@ k_seed_step(GridArgs g, const double* __restrict__ r, const double* __restrict__
             int first) {
   const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   const int nparts = gridDim.x * gridDim.y * gridDim.z;
-  seed_step_tile<TX, TY, KZ>(g, r, p, q, rn, pn, qn, dinv, s0, pin, pout, nparts, st, local, first, blockIdx.x,
-                             blockIdx.y, blockIdx.z, bid);
+  seed_step_tile<TX, TY, KZ, XS>(g, r, p, q, rn, pn, qn, dinv, s0, pin, pout, nparts, st, local, first, blockIdx.x,
+                                 blockIdx.y, blockIdx.z, bid);
 }
 
 // Block blk of the nblk blocks of one seed update (grid-stride over the n entries).
@@ -937,12 +961,17 @@ template <int BB, typename YV, typename PV>
 __device__ __forceinline__ void block_update_block(long long n3, const double* __restrict__ R,
                                                   const double* __restrict__ R0, YV* __restrict__ Y,
                                                   PV* __restrict__ P, int J, const SolveState* __restrict__ st,
-                                                  int f, int blk, int nblk) {
+                                                  int f, int blk, int nblk, const double* __restrict__ rscale) {
   for (long long e = blk * (long long)BU_T + threadIdx.x; e < n3; e += (long long)nblk * BU_T) {
     double rl[BB];
     rl[0] = R0[e];
 #pragma unroll
     for (int l = 1; l < BB; ++l) rl[l] = R[(long long)l * n3 + e];
+    if (rscale) {  // a ring of M^-1/2 r: back to the scaled residuals
+      const double sc = rscale[e];
+#pragma unroll
+      for (int l = 0; l < BB; ++l) rl[l] *= sc;
+    }
     for (int j = 0; j < J; ++j) {
       if (!st->apply[f][j]) continue;
       const double* c = st->cf[f][j][0];
@@ -970,8 +999,9 @@ template <int BB, typename YV, typename PV>
 __global__ void __launch_bounds__(BU_T) k_block_update(long long n3, const double* __restrict__ R,
                                                        const double* __restrict__ R0, YV* __restrict__ Y,
                                                        PV* __restrict__ P, int J,
-                                                       const SolveState* __restrict__ st, int f) {
-  block_update_block<BB, YV, PV>(n3, R, R0, Y, P, J, st, f, blockIdx.x, gridDim.x);
+                                                       const SolveState* __restrict__ st, int f,
+                                                       const double* __restrict__ rscale) {
+  block_update_block<BB, YV, PV>(n3, R, R0, Y, P, J, st, f, blockIdx.x, gridDim.x, rscale);
 }
 
 // ---------------------------------------------------------------------------
@@ -1015,7 +1045,7 @@ __global__ void __launch_bounds__(BU_T) k_block_update_batch(const BatchJob* __r
   while (j + 1 < njobs && (int)blockIdx.x >= jobs[j + 1].bu0) ++j;
   const BatchJob& jb = jobs[j];
   block_update_block<BB, double2, double2>(3 * jb.g.nn, jb.R, jb.R, jb.Y, jb.P, jb.J, jb.st, 0,
-                                           (int)blockIdx.x - jb.bu0, jb.nbu);
+                                           (int)blockIdx.x - jb.bu0, jb.nbu, nullptr);
 }
 
 // the leading SolveHead of every job's state, contiguous, for one copy to the host
@@ -1029,12 +1059,13 @@ __global__ void k_gather_heads(const BatchJob* __restrict__ jobs, int njobs, Sol
 template <typename YV, typename PV>
 __global__ void __launch_bounds__(UPD_T) k_seed_init(long long n3, const double* __restrict__ gv, double* r0,
                                                      double* pold, YV* Y, PV* P, int J,
-                                                     double* __restrict__ partials, SolveState* st) {
+                                                     double* __restrict__ partials, SolveState* st,
+                                                     const double* __restrict__ r0_scale) {
   __shared__ double red[UPD_T / 64];
   double acc = 0.0;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n3; e += (long long)gridDim.x * blockDim.x) {
     const double v = gv[e];
-    r0[e] = v;
+    r0[e] = r0_scale ? r0_scale[e] * v : v;  // the residual ring of the unscaled seed form holds M^-1/2 r
     pold[e] = 0.0;
     for (int j = 0; j < J; ++j) {
       stv(Y, (long long)j * n3 + e, cplx{0.0, 0.0});
@@ -1268,7 +1299,7 @@ __global__ void k_ring_receivers(GridArgs g, const double* __restrict__ R, int B
                           0 * g.nn + node_of(g, i, j + 1, ks), 1 * g.nn + node_of(g, i, j, ks)};
   const double w[4] = {hx * inva, hy * inva, -hx * inva, -hy * inva};
   double acc = 0.0;
-  for (int m = 0; m < 4; ++m) acc += w[m] * dinv[e[m]] * rv[e[m]];
+  for (int m = 0; m < 4; ++m) acc += w[m] * (dinv ? dinv[e[m]] : 1.0) * rv[e[m]];
   hq[idx] = acc;
 }
 
@@ -1326,7 +1357,7 @@ __global__ void k_ring_fields(GridArgs g, const double* __restrict__ U, int T, c
   const int c = storage_to_node(g, e, &node);
   if (c < 0) return;
   const long long n3 = 3 * g.nn;
-  const double d = dinv[c * g.nn + node];
+  const double d = dinv ? dinv[c * g.nn + node] : 1.0;
   for (int t = 0; t < T; ++t) fields[(long long)t * nstore + e] = d * U[(long long)t * n3 + c * g.nn + node];
 }
 
@@ -1344,7 +1375,7 @@ __global__ void k_ring_field_receivers(GridArgs g, const double* __restrict__ U,
                           0 * g.nn + node_of(g, i, j + 1, ks), 1 * g.nn + node_of(g, i, j, ks)};
   const double w[4] = {hx * inva, hy * inva, -hx * inva, -hy * inva};
   double acc = 0.0;
-  for (int m = 0; m < 4; ++m) acc += w[m] * dinv[e[m]] * u[e[m]];
+  for (int m = 0; m < 4; ++m) acc += w[m] * (dinv ? dinv[e[m]] : 1.0) * u[e[m]];
   d[(long long)ch * n_rx + r] = acc;
 }
 
@@ -1789,18 +1820,18 @@ void launch_to_complex(long long n, const double* x, double2* y, hipStream_t s) 
 
 template <typename YV, typename PV>
 static void seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, YV* Y, PV* P, int J,
-                      Reduce red, SolveState* st, hipStream_t s) {
+                      Reduce red, SolveState* st, hipStream_t s, const double* r0_scale) {
   const long long n3 = 3 * g.nn;
   hipLaunchKernelGGL((k_seed_init<YV, PV>), dim3(UPD_BLOCKS), dim3(UPD_T), 0, s, n3, gvec, r0, pold, Y, P, J,
-                     red.partials + kReduceSlots, st);
+                     red.partials + kReduceSlots, st, r0_scale);
 }
 void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, double2* Y, double2* P,
-                      int J, Reduce red, SolveState* st, hipStream_t s) {
-  seed_init(g, gvec, r0, pold, Y, P, J, red, st, s);
+                      int J, Reduce red, SolveState* st, hipStream_t s, const double* r0_scale) {
+  seed_init(g, gvec, r0, pold, Y, P, J, red, st, s, r0_scale);
 }
 void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, double2* Y, float2* P,
-                      int J, Reduce red, SolveState* st, hipStream_t s) {
-  seed_init(g, gvec, r0, pold, Y, P, J, red, st, s);
+                      int J, Reduce red, SolveState* st, hipStream_t s, const double* r0_scale) {
+  seed_init(g, gvec, r0, pold, Y, P, J, red, st, s, r0_scale);
 }
 
 // Seed stencil tile shapes (TX x TY node columns, KZ planes per block); the
@@ -1917,10 +1948,12 @@ void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold,
 #undef TEM_SEED_CASE
 }
 
-// The one-kernel seed step uses the two-plane tile where the grid's tile
-// choice is the two-plane one, else the one-plane tile.
+// The one-kernel seed step uses the (64, 8, 2) tile (g.step_kz = 2) or the
+// (64, 8, 1) tile.  With three staged vectors the two-plane tile was faster
+// at 64^3 and 128^3 alike (15.3 and 126 us against 21.4 and 180 us per step
+// in a standalone timing), unlike the two-kernel stencil at 128^3.
 static dim3 seed_step_grid(const GridArgs& g, bool* two_plane) {
-  *two_plane = pick_seed_tile(g) == 20;
+  *two_plane = g.step_kz != 1;
   const int kz = *two_plane ? 2 : 1;
   return dim3((g.nx + 63) / 64, (g.ny + 7) / 8, (g.nz + kz - 1) / kz);
 }
@@ -1940,12 +1973,11 @@ void launch_seed_step(const GridArgs& g, const double* r, const double* p, const
   const double* pin = red.partials + (size_t)in * 4 * kReduceSlots;
   double* pout = red.partials + (size_t)(1 - in) * 4 * kReduceSlots;
   if (first) pout = red.partials;  // step 0's partials: set 0
-  if (two)
-    put(k, k_seed_step<64, 8, 2>, grid, block, 0u, t0, t1, g, r, p, q, rn, pn, qn, dinv, s0, pin, pout, st, local,
-        first);
-  else
-    put(k, k_seed_step<64, 8, 1>, grid, block, 0u, t0, t1, g, r, p, q, rn, pn, qn, dinv, s0, pin, pout, st, local,
-        first);
+#define TEM_STEP(X, Y, Z, XS) \
+  put(k, k_seed_step<X, Y, Z, XS>, grid, block, 0u, t0, t1, g, r, p, q, rn, pn, qn, dinv, s0, pin, pout, st, local, first)
+  if (two) TEM_STEP(64, 8, 2, true);
+  else TEM_STEP(64, 8, 1, true);
+#undef TEM_STEP
 }
 
 void launch_shift_block_step(const GridArgs& g, int J, Reduce red, SolveState* st, Sink& k, int f) {
@@ -2002,23 +2034,23 @@ void launch_gather_heads(const BatchJob* jobs, int njobs, SolveHead* out, Sink& 
 
 template <typename YV, typename PV>
 static void block_update(const GridArgs& g, const double* R, const double* R0, YV* Y, PV* P, int J, int B,
-                         const SolveState* st, Sink& k, int f, int max_blocks) {
+                         const SolveState* st, Sink& k, int f, int max_blocks, const double* rs) {
   const long long n3 = 3 * g.nn;
   const dim3 grid(grid_1d(n3, BU_T, max_blocks)), block(BU_T);
   switch (B) {
-    case 16: put(k, k_block_update<16, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, R0, Y, P, J, st, f); break;
-    case 32: put(k, k_block_update<32, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, R0, Y, P, J, st, f); break;
-    case 64: put(k, k_block_update<64, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, R0, Y, P, J, st, f); break;
-    default: put(k, k_block_update<8, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, R0, Y, P, J, st, f); break;
+    case 16: put(k, k_block_update<16, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, R0, Y, P, J, st, f, rs); break;
+    case 32: put(k, k_block_update<32, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, R0, Y, P, J, st, f, rs); break;
+    case 64: put(k, k_block_update<64, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, R0, Y, P, J, st, f, rs); break;
+    default: put(k, k_block_update<8, YV, PV>, grid, block, 0u, nullptr, nullptr, n3, R, R0, Y, P, J, st, f, rs); break;
   }
 }
 void launch_block_update(const GridArgs& g, const double* R, const double* R0, double2* Y, double2* P, int J, int B,
-                         const SolveState* st, Sink& k, int f, int max_blocks) {
-  block_update(g, R, R0, Y, P, J, B, st, k, f, max_blocks);
+                         const SolveState* st, Sink& k, int f, int max_blocks, const double* rscale) {
+  block_update(g, R, R0, Y, P, J, B, st, k, f, max_blocks, rscale);
 }
 void launch_block_update(const GridArgs& g, const double* R, const double* R0, double2* Y, float2* P, int J, int B,
-                         const SolveState* st, Sink& k, int f, int max_blocks) {
-  block_update(g, R, R0, Y, P, J, B, st, k, f, max_blocks);
+                         const SolveState* st, Sink& k, int f, int max_blocks, const double* rscale) {
+  block_update(g, R, R0, Y, P, J, B, st, k, f, max_blocks, rscale);
 }
 
 void launch_accumulate(const GridArgs& g, int J, const float2* X, double2* Y, int sign, unsigned long long mask,
