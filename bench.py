@@ -46,7 +46,7 @@ def algorithmic_bytes(kind, ctx_dims, J_apply, B, precision=0, one_kernel=False)
 
 # HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE runs, keyed by the
 # kernel source it was measured on (bytes per launch; see profiles/); None once the source changes
-TRAFFIC = {("2006cd29817b", "graded64", "seed_stencil"): (13126.7 + 12538.6) * 1024.0}
+TRAFFIC = {("12aa4a597ccf", "graded64", "seed_step"): (15889.2 + 18802.4) * 1024.0}
 
 
 def lumped_mass_storage(wl):
@@ -419,7 +419,7 @@ def main():
                                one_kernel)
     # the two-pass form samples no kernel times (its launches are not profiled)
     achieved = nbytes / avg_s / 1e9 if avg_s > 0 else None
-    names = ["seed_cg" if one_kernel else "seed_stencil", "seed_update", "block_update"]
+    names = ["seed_step" if one_kernel else "seed_stencil", "seed_update", "block_update"]
     out = {
         "metric": METRIC,
         "value": upd / dt,
