@@ -70,7 +70,37 @@ __device__ __forceinline__ cplx zero_of(cplx) { return {0.0, 0.0}; }
 __device__ __forceinline__ int flat_tid() { return threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z); }
 __device__ __forceinline__ int flat_threads() { return blockDim.x * blockDim.y * blockDim.z; }
 
-// Deterministic block sum (wave64 shuffles, then the waves in fixed order);
+// v as held by lane l of the wavefront (l the same in every lane)
+__device__ inline double from_lane(double v, int l) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)bits, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// v of another lane of the same row of 16 lanes, by a DPP control (both
+// 32-bit halves moved by the same pattern)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum of v over the 64 lanes of a full wavefront, the same value in every
+// lane and in a fixed order: DPP steps inside each row of 16 lanes (pairs,
+// quads, then rotations by 4 and 8 lanes), then the four row sums read from
+// lanes 0, 16, 32, 48.  Register-to-register moves, no LDS round trips.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x124>(v);  // row_ror:4
+  v += dpp_f64<0x128>(v);  // row_ror:8
+  return (from_lane(v, 0) + from_lane(v, 16)) + (from_lane(v, 32) + from_lane(v, 48));
+}
+
+// Deterministic block sum (wave sums, then the waves in fixed order);
 // the result is valid in thread 0.  lds needs one double per wave.
 // The same two reductions for a block of NT threads known at compile time
 // (thread index tid): no read of the block size from the dispatch packet.
@@ -78,7 +108,7 @@ __device__ __forceinline__ int flat_threads() { return blockDim.x * blockDim.y *
 // thread (each sums the wave totals in the same fixed order).
 template <int NT>
 __device__ __forceinline__ double block_sum_n(double v, double* lds, int tid) {
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
+  v = wave_sum(v);
   const int lane = tid % kWave, wid = tid / kWave;
   __syncthreads();
   if (lane == 0) lds[wid] = v;
@@ -90,7 +120,7 @@ __device__ __forceinline__ double block_sum_n(double v, double* lds, int tid) {
 }
 template <int NT>
 __device__ __forceinline__ double block_total_n(double v, double* lds, int tid) {
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
+  v = wave_sum(v);
   const int lane = tid % kWave, wid = tid / kWave;
   __syncthreads();
   if (lane == 0) lds[wid] = v;
@@ -101,7 +131,7 @@ __device__ __forceinline__ double block_total_n(double v, double* lds, int tid) 
 }
 
 __device__ double block_sum(double v, double* lds) {
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
+  v = wave_sum(v);
   const int tid = flat_tid();
   const int lane = tid % kWave, wid = tid / kWave;
   __syncthreads();
@@ -488,13 +518,6 @@ constexpr int UPD_PF = 4;        // elements per thread loaded ahead of the upda
 
 // Fixed-order sum of n partials written by the previous kernel (every block
 // of the reading kernel computes the same value; no inter-block traffic).
-// v as held by lane l of the wavefront (l the same in every lane)
-__device__ inline double from_lane(double v, int l) {
-  const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)bits, l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), l);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
 
 // ---------------------------------------------------------------------------
 // Seed CG on A0 = A + s0, iteration k (local = k mod B):
@@ -622,8 +645,7 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(TX 
 template <int NT>
 __device__ __forceinline__ void block_total4_n(double v[4], double (*lds)[(NT + kWave - 1) / kWave], int tid) {
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
-    for (int off = kWave / 2; off > 0; off >>= 1) v[m] += __shfl_down(v[m], off, kWave);
+  for (int m = 0; m < 4; ++m) v[m] = wave_sum(v[m]);
   const int lane = tid % kWave, wid = tid / kWave;
   __syncthreads();
   if (lane == 0)
@@ -714,7 +736,12 @@ __device__ __forceinline__ void seed_step_tile(const GridArgs& g, const double* 
     if constexpr (XS) {
       const double mi = d * d;
       const double qv = mi * kp + s0 * pv;
-      const double m = d > 0.0 ? 1.0 / mi : 0.0;
+      // M = 1 / mi: the hardware reciprocal and one Newton step (a weight of
+      // the inner products, good to an ulp; a full division is ten dependent
+      // instructions)
+      const double r0 = __builtin_amdgcn_rcp(mi);
+      const double r1 = fma(fma(-mi, r0, 1.0), r0, r0);
+      const double m = d > 0.0 ? r1 : 0.0;
       const double mq = m * qv;
       qn[e] = qv;
       acc[0] += m * rv * rv;
@@ -733,8 +760,7 @@ __device__ __forceinline__ void seed_step_tile(const GridArgs& g, const double* 
   stencil_block3d<TX, TY, KZ, !XS>(g, dinv, bx, by, bz, fetch, pre, combine, emit);
   // fixed-order block sums of the four products
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
-    for (int off = kWave / 2; off > 0; off >>= 1) acc[m] += __shfl_down(acc[m], off, kWave);
+  for (int m = 0; m < 4; ++m) acc[m] = wave_sum(acc[m]);
   const int lane = tid % kWave, wid = tid / kWave;
   __syncthreads();
   if (lane == 0)
