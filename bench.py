@@ -46,7 +46,7 @@ def algorithmic_bytes(kind, ctx_dims, J_apply, B, precision=0, one_kernel=False)
 
 # HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE runs, keyed by the
 # kernel source it was measured on (bytes per launch; see profiles/); None once the source changes
-TRAFFIC = {("12aa4a597ccf", "graded64", "seed_step"): (15889.2 + 18802.4) * 1024.0}
+TRAFFIC = {("21ea88b041c5", "graded64", "seed_step"): (15534.7 + 18802.5) * 1024.0}
 
 
 def lumped_mass_storage(wl):

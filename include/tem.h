@@ -140,7 +140,9 @@ typedef struct {
  * (a tensor grid of hexahedra with edge unknowns instead of the paper's
  * tetrahedra), inside the PEC box of the Sec. 2.1 boundary condition.  device: HIP device ordinal.  hip_stream: a hipStream_t
  * cast to void*, or NULL for the default stream.  On success *ctx owns device
- * memory for the operator coefficients; no conductivity is set yet. */
+ * memory for the operator coefficients; no conductivity is set yet.  Grids
+ * whose real edge field 3 (nx+1)(ny+1)(nz+1) doubles reaches 4 GiB (about
+ * 560^3 cells) return TEM_EINVAL. */
 int tem_setup_grid(tem_ctx **ctx, int nx, int ny, int nz,
                    const double *hx, const double *hy, const double *hz,
                    int k_surface, int device, void *hip_stream);

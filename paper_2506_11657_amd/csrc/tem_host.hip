@@ -1357,6 +1357,9 @@ int tem_setup_grid(tem_ctx** out, int nx, int ny, int nz, const double* hx, cons
   }
   c->seed_one_kernel = seed_one_kernel_for(g, n_cu);
   if (tem::seed_step_blocks(g) > tem::kReduceSlots) return fail(nullptr, TEM_EINVAL, "grid too large: more seed tiles than partial-sum slots");
+  // the seed kernels address a 3 nn real field by 32-bit byte offsets
+  if (3.0 * (double)g.nn * sizeof(double) >= 4294967296.0)
+    return fail(nullptr, TEM_EINVAL, "grid too large: a real field must stay below 4 GiB");
   c->n3 = 3 * g.nn;
   c->nstore = tem::storage_edges(g);
   if (tem::seed_stencil_blocks(g) > tem::kReduceSlots) return fail(nullptr, TEM_EINVAL, "grid too large: more stencil tiles than partial-sum slots");

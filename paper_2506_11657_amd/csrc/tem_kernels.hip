@@ -163,6 +163,18 @@ __device__ __forceinline__ long long node_of(const GridArgs& g, int i, int j, in
   return ((long long)k * g.py + j) * g.px + i;
 }
 
+// Loads and stores at a 32-bit byte offset from a base pointer: the offset of
+// an entry of a 3 nn real field fits (the library refuses grids where
+// 3 nn * 8 bytes reaches 2^32), and the address then comes from a scalar base
+// plus one 32-bit offset shared by every array of the same layout, with no
+// 64-bit address arithmetic per array.
+__device__ __forceinline__ double ld_at(const double* __restrict__ base, unsigned off) {
+  return *(const double*)((const char*)base + off);
+}
+__device__ __forceinline__ void st_at(double* __restrict__ base, unsigned off, double v) {
+  *(double*)((char*)base + off) = v;
+}
+
 // Map a storage-order edge index to (component, node); returns -1 past the end.
 __device__ __forceinline__ int storage_to_node(const GridArgs& g, long long e, long long* node) {
   const long long nex = (long long)g.nx * g.py * g.pz;
@@ -331,7 +343,8 @@ __device__ void stencil_tile(const GridArgs& g, const double* __restrict__ dinv,
 // previous kernel's partials that yields the recurrence scalars); finally
 // combine(raw) forms the value, which is scaled by M^-1/2 into LDS.  The face
 // fluxes of KZ + 1 planes are formed in LDS from the 1-D width products, and
-// emit(v, c, (K p')_c, raw, M^-1/2) receives every owned edge.
+// emit(off, (K p')_c, raw, M^-1/2) receives every owned edge.  fetch and emit
+// address an entry by its byte offset off = 8 (c nn + node) in a 3 nn field.
 //
 // Staging order: thread (tx, ty) fetches its own node column (i, j) through
 // all KZ + 2 planes, which holds its owned nodes, so their raw values and
@@ -351,7 +364,7 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
   constexpr int NF = (TX + 1) * (TY + 1);                   // flux entries per plane
   constexpr int NB = 2 * (TX + 2) + 2 * TY;                 // border entries per plane
   constexpr int NBL = (NP * NB + NT - 1) / NT;              // border entries per thread
-  using Raw = decltype(fetch(0LL, 0));
+  using Raw = decltype(fetch(0u));
   __shared__ double sp[NP][3][TY + 2][TX + 2];
   __shared__ double phi[KZ + 1][3][TY + 1][TX + 1];
   // 1-D weights of the block's flux nodes: x (li = 0..TX), y (lj = 0..TY), z (pl = 0..KZ)
@@ -369,17 +382,20 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
   Raw cr[NP][3];
   double cd[NP][3];
   const bool col = i < g.px && j < g.py;
+  const unsigned cstride = 8u * (unsigned)g.nn;  // bytes per component
+  unsigned coff[NP];
 #pragma unroll
   for (int pl = 0; pl < NP; ++pl) {
     const int kk = k0 - 1 + pl;
     const bool in = col && kk >= 0 && kk < g.pz;
-    const long long v = in ? node_of(g, i, j, kk) : 0;
+    coff[pl] = in ? 8u * (unsigned)node_of(g, i, j, kk) : 0u;
     const bool ownpl = pl >= 1 && pl <= KZ;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      if (SCALED || ownpl) cd[pl][c] = in ? dinv[c * g.nn + v] : 0.0;
+      const unsigned off = coff[pl] + c * cstride;
+      if (SCALED || ownpl) cd[pl][c] = in ? ld_at(dinv, off) : 0.0;
       else cd[pl][c] = 1.0;
-      cr[pl][c] = in ? fetch(v, c) : Raw{};
+      cr[pl][c] = in ? fetch(off) : Raw{};
     }
   }
   Raw br[NBL][3];
@@ -404,11 +420,12 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
     bpos[m] = (pl * (TY + 2) + lj) * (TX + 2) + li;
     const int gi = i0 - 1 + li, gj = j0 - 1 + lj, kk = k0 - 1 + pl;
     const bool in = b < NP * NB && gi >= 0 && gi < g.px && gj >= 0 && gj < g.py && kk >= 0 && kk < g.pz;
-    const long long v = in ? node_of(g, gi, gj, kk) : 0;
+    const unsigned boff = in ? 8u * (unsigned)node_of(g, gi, gj, kk) : 0u;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      bd[m][c] = SCALED ? (in ? dinv[c * g.nn + v] : 0.0) : 1.0;
-      br[m][c] = in ? fetch(v, c) : Raw{};
+      const unsigned off = boff + c * cstride;
+      bd[m][c] = SCALED ? (in ? ld_at(dinv, off) : 0.0) : 1.0;
+      br[m][c] = in ? fetch(off) : Raw{};
     }
   }
   // 1-D weights of the block's flux nodes: entries (TX + 1) + (TY + 1) + (KZ + 1),
@@ -504,10 +521,9 @@ __device__ void stencil_block3d(const GridArgs& g, const double* __restrict__ di
     const double kpx = ohx * (phi[p - 1][1][lj][li] - fy + fz - phi[p][2][lj - 1][li]);
     const double kpy = ohy * (phi[p][2][lj][li - 1] - fz + fx - phi[p - 1][0][lj][li]);
     const double kpz = ohz[z] * (phi[p][0][lj - 1][li] - fx + fy - phi[p][1][lj][li - 1]);
-    const long long v = node_of(g, i, j, kk);
-    emit(v, 0, kpx, cr[p][0], cd[p][0]);
-    emit(v, 1, kpy, cr[p][1], cd[p][1]);
-    emit(v, 2, kpz, cr[p][2], cd[p][2]);
+    emit(coff[p], kpx, cr[p][0], cd[p][0]);
+    emit(coff[p] + cstride, kpy, cr[p][1], cd[p][1]);
+    emit(coff[p] + 2 * cstride, kpz, cr[p][2], cd[p][2]);
   }
 }
 
@@ -582,9 +598,15 @@ __device__ __forceinline__ void seed_stencil_tile(const GridArgs& g, const doubl
     struct RP {
       double r, p;
     };
-    auto fetch = [&](long long v, int c) { return RP{r[c * g.nn + v], pold[c * g.nn + v]}; };
+    auto fetch = [&](unsigned off) { return RP{ld_at(r, off), ld_at(pold, off)}; };
     auto combine = [&](const RP& x) { return x.r + beta * x.p; };
-    auto emit_raw = [&](long long v, int c, double kp, const RP& x, double d) { emit(v, c, kp, combine(x), d); };
+    auto emit_raw = [&](unsigned off, double kp, const RP& x, double d) {
+      const double u = combine(x);
+      const double out = d * kp + s0 * u;
+      st_at(pnew, off, u);
+      st_at(q, off, out);
+      dot += u * out;
+    };
     stencil_block3d<TX, TY, KZ>(g, dinv, bx, by, bz, fetch, pre, combine, emit_raw);
   } else {
     pre();
@@ -720,19 +742,15 @@ __device__ __forceinline__ void seed_step_tile(const GridArgs& g, const double* 
   struct RPQ {
     double r, p, q;
   };
-  auto fetch = [&](long long v, int c) {
-    const long long e = c * g.nn + v;
-    return RPQ{r[e], p[e], q[e]};
-  };
+  auto fetch = [&](unsigned off) { return RPQ{ld_at(r, off), ld_at(p, off), ld_at(q, off)}; };
   auto rnext = [&](const RPQ& x) { return x.r - alpha * x.q; };
   auto combine = [&](const RPQ& x) { return rnext(x) + beta * x.p; };
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  auto emit = [&](long long v, int c, double kp, const RPQ& x, double d) {
-    const long long e = c * g.nn + v;
+  auto emit = [&](unsigned off, double kp, const RPQ& x, double d) {
     const double rv = rnext(x);
     const double pv = combine(x);
-    if (!first) rn[e] = rv;
-    pn[e] = pv;
+    if (!first) st_at(rn, off, rv);
+    st_at(pn, off, pv);
     if constexpr (XS) {
       const double mi = d * d;
       const double qv = mi * kp + s0 * pv;
@@ -743,14 +761,14 @@ __device__ __forceinline__ void seed_step_tile(const GridArgs& g, const double* 
       const double r1 = fma(fma(-mi, r0, 1.0), r0, r0);
       const double m = d > 0.0 ? r1 : 0.0;
       const double mq = m * qv;
-      qn[e] = qv;
+      st_at(qn, off, qv);
       acc[0] += m * rv * rv;
       acc[1] += pv * mq;
       acc[2] += rv * mq;
       acc[3] += qv * mq;
     } else {
       const double qv = d * kp + s0 * pv;
-      qn[e] = qv;
+      st_at(qn, off, qv);
       acc[0] += rv * rv;
       acc[1] += pv * qv;
       acc[2] += rv * qv;
