@@ -252,7 +252,11 @@ int tem_engine_create(tem_engine **eng, int device, int max_jobs);
  * (NULL detaches).  ctx and eng must be on the same device.  Calls on ctx stay
  * synchronous for its caller; several threads, each with its own context,
  * share the engine.  A solve through the engine always uses 64-iteration
- * blocks (tem_solve_opts.block and .profile are ignored). */
+ * blocks (tem_solve_opts.block and .profile are ignored).  Only grids with
+ * fewer 64 x 8 x 2-node seed tiles than the device has compute units (on a
+ * 256-CU MI355X, cubes up to 56^3 cells) use the engine; solves of larger
+ * grids fill the device alone and keep their own launches, whether or not an
+ * engine is attached. */
 int tem_attach_engine(tem_ctx *ctx, tem_engine *eng);
 
 /* Batching statistics: blocks launched, job-blocks (sum over blocks of the jobs

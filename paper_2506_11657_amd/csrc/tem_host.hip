@@ -59,8 +59,12 @@ hipError_t scratch_address(int device, void** out) {
 }
 // Adjoint by one multi-shift solve per receiver row up to this many receivers
 // (about n_rx seed sweeps); beyond it one batched COCG over the J shifted
-// systems (about J complex solves) costs less.
-constexpr int kAdjointMultishiftMaxRx = 64;
+// systems (about J complex solves).  Measured on the 64^3 differentiation
+// workload (30 receivers, J = 22): the rows took 364 s (12.1 s each, four at
+// a time); the COCG had not finished after 1044 s (6 of 22 systems still
+// active at 490k iterations), so the rows are cheaper below 1044 / 12.1 = 86
+// receivers at least.
+constexpr int kAdjointMultishiftMaxRx = 86;
 // precision 1: the sweep (FP64 iterates y_j, complex FP32 directions p_j) stops
 // at the recursive tolerance kSweepTolFP32, below the M-norm error that the
 // FP32 directions leave (a few 1e-8); FP64 residual refinement then drives
@@ -130,6 +134,7 @@ struct tem_ctx {
   std::vector<DevBuf> Y;  // per source (kept) or one
   // stored forward state for the adjoint
   bool seed_one_kernel = true;  // seed CG form (seed_one_kernel_for)
+  bool engine_batches = false;  // solves go to an attached engine (uses_engine)
   bool fwd_meta = false;   // the last forward's sources, receivers, poles and options are recorded
   bool fwd_valid = false;  // ... and its solutions are kept on the device
   int fwd_J = 0, fwd_T = 0, fwd_nsrc = 0, fwd_nrx = 0;
@@ -178,6 +183,14 @@ int overlap_blocks() {
 // (128^3: 169 us against 148 us per iteration).  TEM_SEED=hs or =one forces
 // a form.  The batched engine, whose jobs fill the device together, uses the
 // two-kernel form.
+// Whether a context's FP64 multi-shift solves go to its attached engine:
+// only when one solve's tiles leave compute units idle (32^3, 48^3 here),
+// where sharing launches with other solves fills the device.  A solve that
+// fills the device alone runs faster on its own streams: 30 adjoint receiver
+// rows at 64^3 took 557 s as 16 batched jobs of the engine's two-kernel
+// iteration, 364 s as four concurrent one-kernel solves.
+bool uses_engine(const tem_ctx* ctx) { return ctx->engine != nullptr && ctx->engine_batches; }
+
 bool seed_one_kernel_for(const GridArgs& g, int n_cu) {
   const char* e = getenv("TEM_SEED");
   if (e && !strcmp(e, "hs")) return false;
@@ -682,7 +695,7 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
                      double s0, const tem_solve_opts& o, int njobs, double2* const* Ys, SolveState* states,
                      double& seconds) {
   if constexpr (std::is_same<PV, double2>::value) {
-    if (ctx->engine) return engine_solve(ctx, shifts_re, shifts_im, s0, o, njobs, Ys, states, seconds);
+    if (uses_engine(ctx)) return engine_solve(ctx, shifts_re, shifts_im, s0, o, njobs, Ys, states, seconds);
   }
   const int J = (int)shifts_re.size();
   const int B = block_length(o.block);
@@ -1356,6 +1369,7 @@ int tem_setup_grid(tem_ctx** out, int nx, int ny, int nz, const double* hx, cons
     g.step_kz = (e && atoi(e) == 17) ? 1 : 2;
   }
   c->seed_one_kernel = seed_one_kernel_for(g, n_cu);
+  c->engine_batches = n_cu > 0 && tem::seed_step_blocks(g) < n_cu;
   if (tem::seed_step_blocks(g) > tem::kReduceSlots) return fail(nullptr, TEM_EINVAL, "grid too large: more seed tiles than partial-sum slots");
   // the seed kernels address a 3 nn real field by 32-bit byte offsets
   if (3.0 * (double)g.nn * sizeof(double) >= 4294967296.0)
@@ -1885,7 +1899,7 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
     if (!strcmp(m, "cocg")) use_rows = false;
     if (!strcmp(m, "multishift")) use_rows = true;
   }
-  const int row_conc = std::min(n_rx, ctx->engine ? tem::kMaxBatchJobs : kMaxConcurrentSolves);
+  const int row_conc = std::min(n_rx, uses_engine(ctx) ? tem::kMaxBatchJobs : kMaxConcurrentSolves);
   const int nH = use_rows ? row_conc : 1;
   if ((rc = ensure(ctx, H, nH * vb)) || (rc = ensure(ctx, Mu, vb)) || (rc = ensure(ctx, Rr, vb)) ||
       (rc = ensure(ctx, Pb, 2 * vb)) || (rc = ensure(ctx, Q, vb)) || (rc = ensure(ctx, z, ctx->n3 * sizeof(double))) ||

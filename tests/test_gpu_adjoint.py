@@ -83,11 +83,13 @@ def test_adjoint_two_sources_sum(tem):
     assert np.allclose(g2, parts[0] + parts[1], rtol=1e-9, atol=1e-12 * np.abs(g2).max())
 
 
-def test_adjoint_many_receivers_cocg_path(tem):
-    """More receivers (70) than the per-receiver multi-shift path takes (64):
-    the batched COCG path gives the same gradient as the oracle."""
+def test_adjoint_many_receivers_cocg_path(tem, monkeypatch):
+    """The batched COCG path of the adjoint (the library takes it above 86
+    receivers; TEM_ADJOINT=cocg selects it here for 70) gives the same
+    gradient as the oracle."""
+    monkeypatch.setenv("TEM_ADJOINT", "cocg")
     wl = W.small_case(9, seed=9, t=W.log_channels(1e-5, 1e-3, 6))
-    wl.receivers = [(i, j) for i in range(9) for j in range(9)][:70]  # > 64: batched COCG
+    wl.receivers = [(i, j) for i in range(9) for j in range(9)][:70]
     fit = rkfit.rkfit(wl.t, 16)
     s, C = rkfit.shifts_and_coefficients(fit)
     P = yee.Problem(wl)
