@@ -31,7 +31,8 @@ def algorithmic_bytes(kind, ctx_dims, J_apply, B, precision=0, one_kernel=False)
        stencil: read r, p_old, M^-1/2, write p_new, q on the 3 nx ny nz owned edges (40 B each);
        one-kernel seed step (in place of stencil + update): read r, w, s, M^-1/2, write
                 s', r', w' on the owned edges (56 B each);
-       update:  read r, q, write r_next on all 3 (nx+1)(ny+1)(nz+1) padded entries (24 B);
+       update:  read r, q, write r_next on all 3 (nx+1)(ny+1)(nz+1) padded entries (24 B; on unscaled
+                vectors it also reads M^-1/2 for the weight of (r, r), which is not counted here);
        block:   read the B residuals (8 B each) and read+write x_j, p_j (64 B per shift;
                 48 B with the FP32 directions of precision 1)."""
     nx, ny, nz = ctx_dims

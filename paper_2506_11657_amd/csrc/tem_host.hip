@@ -741,7 +741,9 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
   // the block's own launch sequence.
   const bool overlap = overlap_updates();
   const bool one_kernel = ctx->seed_one_kernel;
-  const bool unscaled = one_kernel;  // the one-kernel form's ring holds M^-1/2 r
+  // unscaled seed vectors (the ring holds M^-1/2 r): the one-kernel form, and
+  // the two-kernel form on the two tiles the library chooses
+  const bool unscaled = one_kernel || tem::seed_stencil_unscaled_tile(ctx->g);
   const int RS = overlap ? tem::kPhases * B : B;  // ring slots
   // pbuf: p_{k-1}, p_k by parity (two-kernel form), or p_i, p_{i+1} and then
   // q_i, q_{i+1} by parity (one-kernel form)
@@ -763,9 +765,10 @@ int multishift_solve(tem_ctx* ctx, const std::vector<double>& shifts_re, const s
                               timed ? ev[4 * l + 1] : nullptr);
         continue;
       }
-      tem::launch_seed_stencil(g, r, pold, pnew, q, ctx->d_dinv, s0, red, sl.d_state, l, st,
+      tem::launch_seed_stencil(g, r, pold, pnew, q, ctx->d_dinv, s0, red, sl.d_state, l, unscaled, st,
                                timed ? ev[4 * l] : nullptr, timed ? ev[4 * l + 1] : nullptr);
-      tem::launch_seed_update(g, r, q, rn, red, sl.d_state, l, st, timed ? ev[4 * l + 2] : nullptr,
+      tem::launch_seed_update(g, r, q, rn, red, sl.d_state, l, unscaled ? ctx->d_dinv : nullptr, st,
+                              timed ? ev[4 * l + 2] : nullptr,
                               timed ? ev[4 * l + 3] : nullptr);
     }
     if (!overlap && timed) (void)hipEventRecord(ev[4 * B], st.stream);
@@ -1100,7 +1103,9 @@ int lanczos_source(tem_ctx* ctx, int i, const std::vector<double>& shifts_re, co
   int rc;
   SolveSlot& sl = ctx->slots[i];
   const bool one_kernel = ctx->seed_one_kernel;
-  const bool unscaled = one_kernel;  // the one-kernel form's ring holds M^-1/2 r
+  // unscaled seed vectors (the ring holds M^-1/2 r): the one-kernel form, and
+  // the two-kernel form on the two tiles the library chooses
+  const bool unscaled = one_kernel || tem::seed_stencil_unscaled_tile(ctx->g);
   if ((rc = ensure(ctx, sl.R, (size_t)B * n3 * sizeof(double))) ||
       (rc = ensure(ctx, sl.pbuf, (one_kernel ? 4 : 2) * n3 * sizeof(double))) ||
       (rc = ensure(ctx, sl.q, n3 * sizeof(double))) ||
@@ -1172,8 +1177,8 @@ int lanczos_source(tem_ctx* ctx, int i, const std::vector<double>& shifts_re, co
         continue;
       }
       tem::launch_seed_stencil(g, r, pb + (size_t)((l + 1) & 1) * n3, pb + (size_t)(l & 1) * n3, q, ctx->d_dinv, s0,
-                               red, sl.d_state, l, k);
-      tem::launch_seed_update(g, r, q, rn, red, sl.d_state, l, k);
+                               red, sl.d_state, l, unscaled, k);
+      tem::launch_seed_update(g, r, q, rn, red, sl.d_state, l, unscaled ? ctx->d_dinv : nullptr, k);
     }
     if (one_kernel) tem::launch_shift_block_step(g, J, red, sl.d_state, k);
     else tem::launch_shift_block(g, J, red, sl.d_state, k);

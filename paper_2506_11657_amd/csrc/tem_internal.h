@@ -142,12 +142,16 @@ void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double*
                       int J, Reduce red, SolveState* st, hipStream_t s, const double* r0_scale = nullptr);
 void launch_seed_init(const GridArgs& g, const double* gvec, double* r0, double* pold, double2* Y, float2* P,
                       int J, Reduce red, SolveState* st, hipStream_t s, const double* r0_scale = nullptr);
-// with t0 != nullptr the dispatch records its own start (t0) and stop (t1) events
+// with t0 != nullptr the dispatch records its own start (t0) and stop (t1) events.
+// unscaled (only for the tiles seed_stencil_unscaled_tile accepts): the vectors
+// hold M^-1/2 v; the update then gets wd = M^-1/2 to weight (r, r) by M.
+bool seed_stencil_unscaled_tile(const GridArgs& g);
 void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold, double* pnew, double* q,
-                         const double* dinv, double s0, Reduce red, SolveState* st, int local, Sink& k,
-                         hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+                         const double* dinv, double s0, Reduce red, SolveState* st, int local, bool unscaled,
+                         Sink& k, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_seed_update(const GridArgs& g, const double* r, const double* q, double* rnext, Reduce red,
-                        SolveState* st, int local, Sink& k, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+                        SolveState* st, int local, const double* wd, Sink& k, hipEvent_t t0 = nullptr,
+                        hipEvent_t t1 = nullptr);
 // One-kernel seed step `local` (update of step i fused with the stencil of
 // step i + 1): reads r_i, p_i, q_i = A0 p_i, writes r_{i+1} (ring), p_{i+1},
 // q_{i+1}; p and q ping-pong by parity (read slot local & 1); partial sums in

@@ -175,6 +175,17 @@ __device__ __forceinline__ void st_at(double* __restrict__ base, unsigned off, d
   *(double*)((char*)base + off) = v;
 }
 
+// The lumped mass M_e = 1 / (M^-1/2)^2 from the scaling d = M^-1/2 of an edge,
+// zero on the boundary edges (d = 0): the weight of the inner products of the
+// unscaled seed vectors.  Hardware reciprocal plus one Newton step (a weight
+// good to an ulp; a full division is ten dependent instructions).
+__device__ __forceinline__ double mass_weight(double d) {
+  const double mi = d * d;
+  const double r0 = __builtin_amdgcn_rcp(mi);
+  const double r1 = fma(fma(-mi, r0, 1.0), r0, r0);
+  return d > 0.0 ? r1 : 0.0;
+}
+
 // Map a storage-order edge index to (component, node); returns -1 past the end.
 __device__ __forceinline__ int storage_to_node(const GridArgs& g, long long e, long long* node) {
   const long long nex = (long long)g.nx * g.py * g.pz;
@@ -545,8 +556,11 @@ constexpr int UPD_PF = 4;        // elements per thread loaded ahead of the upda
 // bitwise repeatable and no device-scope fences are needed.
 // ---------------------------------------------------------------------------
 // One tile of the seed stencil: tile (bx, by, bz) of the grid, block index bid
-// among the stencil's nst blocks (its partial-sum slot).
-template <int TX, int TY, int KZ, bool B3D>
+// among the stencil's nst blocks (its partial-sum slot).  XS (with B3D): the
+// vectors are unscaled (M^-1/2 v, as in the one-kernel form): the halo stages
+// r and p_old only, the owned edges form q = M^-1 K p + s0 p and the M-weighted
+// (p, q); the update then weights (r, r) by M.
+template <int TX, int TY, int KZ, bool B3D, bool XS = false>
 __device__ __forceinline__ void seed_stencil_tile(const GridArgs& g, const double* __restrict__ r,
                                                   const double* __restrict__ pold, double* __restrict__ pnew,
                                                   double* __restrict__ q, const double* __restrict__ dinv, double s0,
@@ -602,12 +616,12 @@ __device__ __forceinline__ void seed_stencil_tile(const GridArgs& g, const doubl
     auto combine = [&](const RP& x) { return x.r + beta * x.p; };
     auto emit_raw = [&](unsigned off, double kp, const RP& x, double d) {
       const double u = combine(x);
-      const double out = d * kp + s0 * u;
+      const double out = XS ? (d * d) * kp + s0 * u : d * kp + s0 * u;
       st_at(pnew, off, u);
       st_at(q, off, out);
-      dot += u * out;
+      dot += XS ? mass_weight(d) * u * out : u * out;
     };
-    stencil_block3d<TX, TY, KZ>(g, dinv, bx, by, bz, fetch, pre, combine, emit_raw);
+    stencil_block3d<TX, TY, KZ, !XS>(g, dinv, bx, by, bz, fetch, pre, combine, emit_raw);
   } else {
     pre();
     auto load = [&](long long v, int c) { return r[c * g.nn + v] + beta * pold[c * g.nn + v]; };
@@ -619,7 +633,7 @@ __device__ __forceinline__ void seed_stencil_tile(const GridArgs& g, const doubl
 
 // 4 waves per SIMD keeps two 512-thread tiles resident per CU (the LDS of
 // two tiles fits); the staged registers must then fit in 128 VGPRs
-template <int TX, int TY, int KZ, bool B3D>
+template <int TX, int TY, int KZ, bool B3D, bool XS = false>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(TX * TY * KZ > 512 ? 2 : 4))) k_seed_stencil(GridArgs g, const double* __restrict__ r,
                                                           const double* __restrict__ pold,
                                                           double* __restrict__ pnew, double* __restrict__ q,
@@ -627,8 +641,8 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(TX 
                                                           const double* __restrict__ upd_partials,
                                                           double* __restrict__ partials, SolveState* st, int local) {
   const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-  seed_stencil_tile<TX, TY, KZ, B3D>(g, r, pold, pnew, q, dinv, s0, upd_partials, partials, st, local, blockIdx.x,
-                                     blockIdx.y, blockIdx.z, bid);
+  seed_stencil_tile<TX, TY, KZ, B3D, XS>(g, r, pold, pnew, q, dinv, s0, upd_partials, partials, st, local,
+                                         blockIdx.x, blockIdx.y, blockIdx.z, bid);
 }
 
 // ---------------------------------------------------------------------------
@@ -752,17 +766,10 @@ __device__ __forceinline__ void seed_step_tile(const GridArgs& g, const double* 
     if (!first) st_at(rn, off, rv);
     st_at(pn, off, pv);
     if constexpr (XS) {
-      const double mi = d * d;
-      const double qv = mi * kp + s0 * pv;
-      // M = 1 / mi: the hardware reciprocal and one Newton step (a weight of
-      // the inner products, good to an ulp; a full division is ten dependent
-      // instructions)
-      const double r0 = __builtin_amdgcn_rcp(mi);
-      const double r1 = fma(fma(-mi, r0, 1.0), r0, r0);
-      const double m = d > 0.0 ? r1 : 0.0;
-      const double mq = m * qv;
+      const double qv = (d * d) * kp + s0 * pv;
+      const double mq = mass_weight(d) * qv;
       st_at(qn, off, qv);
-      acc[0] += m * rv * rv;
+      acc[0] += mass_weight(d) * rv * rv;
       acc[1] += pv * mq;
       acc[2] += rv * mq;
       acc[3] += qv * mq;
@@ -806,11 +813,12 @@ k_seed_step(GridArgs g, const double* __restrict__ r, const double* __restrict__
 }
 
 // Block blk of the nblk blocks of one seed update (grid-stride over the n entries).
+// wd != nullptr: unscaled vectors, (r, r) weighted by M from wd = M^-1/2.
 __device__ __forceinline__ void seed_update_block(long long n, const double* __restrict__ r,
                                                   const double* __restrict__ q, double* __restrict__ rnext,
                                                   const double* __restrict__ st_partials, int n_st,
                                                   double* __restrict__ partials, SolveState* st, int local, int blk,
-                                                  int nblk) {
+                                                  int nblk, const double* __restrict__ wd) {
   __shared__ double red[UPD_T / 64];
   const int tid = threadIdx.x;
   // requested first, so that their round trips overlap the loads of r and q
@@ -823,12 +831,13 @@ __device__ __forceinline__ void seed_update_block(long long n, const double* __r
   // that their latency overlaps the sum of the stencil's partials
   const long long stride = (long long)nblk * UPD_T;
   const long long e0 = blk * (long long)UPD_T + tid;
-  double rv[UPD_PF], qv[UPD_PF];
+  double rv[UPD_PF], qv[UPD_PF], dv[UPD_PF];
 #pragma unroll
   for (int m = 0; m < UPD_PF; ++m) {
     const long long e = e0 + m * stride;
     rv[m] = e < n ? r[e] : 0.0;
     qv[m] = e < n ? q[e] : 0.0;
+    dv[m] = (wd && e < n) ? wd[e] : 1.0;
   }
   // fixed-order sum: this thread's partials in index order, then the block
   double sp = tid < n_st ? part0 : 0.0;
@@ -851,13 +860,13 @@ __device__ __forceinline__ void seed_update_block(long long n, const double* __r
     if (e < n) {
       const double v = rv[m] - alpha * qv[m];
       rnext[e] = v;
-      acc += v * v;
+      acc += (wd ? mass_weight(dv[m]) : 1.0) * v * v;
     }
   }
   for (long long e = e0 + UPD_PF * stride; e < n; e += stride) {
     const double v = r[e] - alpha * q[e];
     rnext[e] = v;
-    acc += v * v;
+    acc += (wd ? mass_weight(wd[e]) : 1.0) * v * v;
   }
   const double s = block_sum_n<UPD_T>(acc, red, tid);
   if (tid == 0) partials[blk] = s;
@@ -866,8 +875,9 @@ __device__ __forceinline__ void seed_update_block(long long n, const double* __r
 __global__ void __launch_bounds__(UPD_T) k_seed_update(long long n, const double* __restrict__ r,
                                                        const double* __restrict__ q, double* __restrict__ rnext,
                                                        const double* __restrict__ st_partials, int n_st,
-                                                       double* __restrict__ partials, SolveState* st, int local) {
-  seed_update_block(n, r, q, rnext, st_partials, n_st, partials, st, local, blockIdx.x, gridDim.x);
+                                                       double* __restrict__ partials, SolveState* st, int local,
+                                                       const double* __restrict__ wd) {
+  seed_update_block(n, r, q, rnext, st_partials, n_st, partials, st, local, blockIdx.x, gridDim.x, wd);
 }
 
 // Per-shift recurrences for one block of B seed steps, replayed from the
@@ -1074,7 +1084,7 @@ __global__ void __launch_bounds__(UPD_T) k_seed_update_batch(const BatchJob* __r
   const BatchJob& jb = jobs[blockIdx.x / UPD_BLOCKS];
   const long long n3 = 3 * jb.g.nn;
   seed_update_block(n3, jb.R + (long long)local * n3, jb.q, jb.R + (long long)((local + 1) % B) * n3, jb.part_st,
-                    jb.ntiles, jb.part_up, jb.st, local, blockIdx.x % UPD_BLOCKS, UPD_BLOCKS);
+                    jb.ntiles, jb.part_up, jb.st, local, blockIdx.x % UPD_BLOCKS, UPD_BLOCKS, nullptr);
 }
 
 __global__ void __launch_bounds__(64) k_shift_block_batch(const BatchJob* __restrict__ jobs) {
@@ -1954,13 +1964,28 @@ static void put(Sink& k, void (*kernel)(P...), dim3 grid, dim3 block, uint32_t s
   if (k.err == hipSuccess) k.last = node;
 }
 
+bool seed_stencil_unscaled_tile(const GridArgs& g) {
+  const int v = pick_seed_tile(g);
+  return v == 17 || v == 20;
+}
+
 void launch_seed_stencil(const GridArgs& g, const double* r, const double* pold, double* pnew, double* q,
-                         const double* dinv, double s0, Reduce red, SolveState* st, int local, Sink& k,
-                         hipEvent_t t0, hipEvent_t t1) {
+                         const double* dinv, double s0, Reduce red, SolveState* st, int local, bool unscaled,
+                         Sink& k, hipEvent_t t0, hipEvent_t t1) {
   const int v = pick_seed_tile(g);
   const TileShape t = kSeedTiles[v];
   const dim3 grid = seed_stencil_grid(g), block(t.tx, t.ty);
   const double* up = red.partials + kReduceSlots;
+  if (unscaled && v == 17) {
+    put(k, k_seed_stencil<64, 8, 1, true, true>, grid, block, 0u, t0, t1, g, r, pold, pnew, q, dinv, s0, up,
+        red.partials, st, local);
+    return;
+  }
+  if (unscaled && v == 20) {
+    put(k, k_seed_stencil<64, 8, 2, true, true>, grid, block, 0u, t0, t1, g, r, pold, pnew, q, dinv, s0, up,
+        red.partials, st, local);
+    return;
+  }
 #define TEM_SEED_CASE(I, X, Y, Z)                                                                            \
   case I:                                                                                                    \
     put(k, k_seed_stencil<X, Y, Z, (I >= 10)>, grid, block, 0u, t0, t1, g, r, pold, pnew, q, dinv, s0, up,      \
@@ -2030,12 +2055,12 @@ void launch_shift_block_step(const GridArgs& g, int J, Reduce red, SolveState* s
 }
 
 void launch_seed_update(const GridArgs& g, const double* r, const double* q, double* rnext, Reduce red,
-                        SolveState* st, int local, Sink& k, hipEvent_t t0, hipEvent_t t1) {
+                        SolveState* st, int local, const double* wd, Sink& k, hipEvent_t t0, hipEvent_t t1) {
   const long long n3 = 3 * g.nn;
   const dim3 sg = seed_stencil_grid(g);
   const int nst = sg.x * sg.y * sg.z;
   put(k, k_seed_update, dim3(UPD_BLOCKS), dim3(UPD_T), 0u, t0, t1, n3, r, q, rnext, (const double*)red.partials, nst,
-      red.partials + kReduceSlots, st, local);
+      red.partials + kReduceSlots, st, local, wd);
 }
 
 int seed_stencil_blocks(const GridArgs& g) {
