@@ -47,7 +47,7 @@ def algorithmic_bytes(kind, ctx_dims, J_apply, B, precision=0, one_kernel=False)
 
 # HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE runs, keyed by the
 # kernel source it was measured on (bytes per launch; see profiles/); None once the source changes
-TRAFFIC = {("21ea88b041c5", "graded64", "seed_step"): (15534.7 + 18802.5) * 1024.0}
+TRAFFIC = {("13fbe21b6c10", "graded64", "seed_step"): (15655.5 + 18804.6) * 1024.0}
 
 
 def lumped_mass_storage(wl):
