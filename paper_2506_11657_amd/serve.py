@@ -15,8 +15,11 @@ batched launches, one seed stencil and one seed update launch per iteration
 for all of them and one shift-block and block-update launch per 64
 iterations for all their poles, replayed as HIP graphs; a request joins the
 batch at the next 64-iteration boundary after it is admitted and leaves it
-when its shifts have converged.  Without it, each request replays its own
-solver graphs on its own streams and the requests overlap on the device.
+when its shifts have converged.  The library sends only the solves of grids
+too small to fill the device to the engine; larger ones (64^3 and up on
+MI355X) run their own launches, as they do without an engine.  Without it,
+each request replays its own solver graphs on its own streams and the
+requests overlap on the device.
 
 Each request's arithmetic is independent of the others (its own buffers,
 fixed-order reductions whose order does not depend on the batch), so its
@@ -38,8 +41,9 @@ from . import tem
 def footprint_bytes(nx, ny, nz, J, n_src, kind, block=64, n_rx=1, concurrent=4):
     """Device bytes a request needs (the library's allocations for it):
     operator arrays; one solver workspace per concurrent multi-shift solve
-    (residual ring of `block` vectors, 3x that with overlapped updates, seed p and q, right-hand side, per-shift
-    p_j); the solutions y_j of every concurrent source (of every source for the
+    (residual ring of `block` vectors, 3x that with overlapped updates, the
+    seed's p and q in two slots each, right-hand side, per-shift p_j, 4 MiB of
+    partial sums); the solutions y_j of every concurrent source (of every source for the
     adjoint, which keeps them); the residual and contraction scratch; for the
     adjoint, its right-hand sides per concurrent receiver row and its COCG
     vectors."""
@@ -51,7 +55,7 @@ def footprint_bytes(nx, ny, nz, J, n_src, kind, block=64, n_rx=1, concurrent=4):
     if kind == "adjoint":
         slots = max(slots, min(n_rx, concurrent))
     ring = 3 * block if os.environ.get("TEM_OVERLAP") == "1" else block   # 3 blocks with overlapped updates
-    slot = 8 * n3 * (ring + 4) + vec + (1 << 20)
+    slot = 8 * n3 * (ring + 6) + vec + (4 << 20)
     keep = vec * (n_src if kind == "adjoint" else conc)
     scratch = vec + 24 * n3
     adj = 0
