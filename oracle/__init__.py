@@ -12,6 +12,8 @@ Modules
   rkfit    the shared-pole rational family of Sec. 3.2, eq. (ratfam), fitted
            by RKFIT, plus the error measures eq. (error)/(uniform_error) and
            the degree arithmetic of Table 1;
+  single   the single-time best approximation of type [m/m] of Sec. 3.1 and
+           its evaluation eq. (rba) by direct solves of t_k K - xi_i M;
   direct   shifted solves by banded and sparse LU, the residue contraction
            eq. (rmj) as S R, receiver data, dense expm references, and the
            adjoint gradient of Sec. 4;
