@@ -292,6 +292,53 @@ def weights_study(args):
     print(json.dumps({"weights_study": out}), flush=True)
 
 
+def single_time_bench(args):
+    """The single-time baseline (Sec. 3.1, eq. (rba)) against the shared-pole
+    family (Sec. 3.2) on the same workload and device: the type-[m/m] best
+    approximation (m = 14, the paper's degree) needs ceil(m/2) systems per
+    channel, J T in all, against the J shared ones.  Both forwards run with
+    fields; each is timed once after an untimed warm-up call.  Reported: wall
+    time, systems, summed seed iterations, unknown-updates, and the deviation
+    of dB_z/dt between the two (relative to the channel value)."""
+    import torch
+    import tem_workloads as W
+    from paper_2506_11657_amd import tem
+    wl = {"graded64": W.cfg_graded64, "plain16": W.cfg_plain16, "blocky128": W.cfg_blocky128}[args.config]()
+    torch.cuda.set_device(0)
+    ctx = tem.Context.from_workload(wl)
+    T = len(wl.t)
+    fields = torch.zeros((1, T, ctx.n_storage), dtype=torch.float64, device="cuda")
+    xs, a, a0, err_single = tem.poles_single(args.single_degree)
+    xi, c, err = tem.poles(wl.t, wl.degree)
+    out = {"workload": wl.name, "channels": T}
+    runs = {}
+    for name in ("shared", "single"):
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if name == "shared":
+                d, st = ctx.forward(wl.loops, wl.receivers, xi, c, fields=fields)
+            else:
+                d, st = ctx.forward_single(wl.loops, wl.receivers, wl.t, xs, a, a0, fields=fields)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            print("%s forward (%s): %.2f s, %d systems, %d seed iterations" % (name, "warm-up" if rep == 0 else "timed",
+                  dt, st["n_shifts"], st["iterations"]), file=sys.stderr, flush=True)
+        runs[name] = d[0, :, 0].copy()
+        out[name] = {"seconds": dt, "systems": st["n_shifts"], "seed_iterations": st["iterations"],
+                     "unknown_updates": st["unknown_updates"], "converged": bool(st["converged"]),
+                     "max_true_res": float(max(st["true_res"][:min(64, T)]))}
+    out["single"]["degree"] = args.single_degree
+    out["single"]["uniform_error"] = err_single
+    out["shared"]["degree"] = wl.degree
+    out["shared"]["max_channel_error"] = float(err.max())
+    out["time_ratio_single_over_shared"] = out["single"]["seconds"] / out["shared"]["seconds"]
+    rel = np.abs(runs["single"] - runs["shared"]) / np.abs(runs["shared"])
+    out["dbz_dt_rel_dev"] = [float(v) for v in rel]
+    ctx.close()
+    print(json.dumps({"single_time": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -327,6 +374,9 @@ def main():
     ap.add_argument("--time-budget", type=float, default=900.0, help="--adjoint: stop starting FD cells after this")
     ap.add_argument("--weights-study", action="store_true",
                     help="instead of the forward benchmark, the weighted-RKFIT evaluation on the 64^3 workload")
+    ap.add_argument("--single-time", action="store_true",
+                    help="compare the single-time baseline (Sec. 3.1) with the shared-pole forward")
+    ap.add_argument("--single-degree", type=int, default=14)
     ap.add_argument("--serve-max-active", type=int, default=4)
     ap.add_argument("--serve-first", type=int, default=0,
                     help="serve requests serve_first .. serve_first + serve - 1 of the trace")
@@ -350,6 +400,8 @@ def main():
         return adjoint_bench(args)
     if args.weights_study:
         return weights_study(args)
+    if args.single_time:
+        return single_time_bench(args)
 
     wl = {"graded64": W.cfg_graded64, "plain16": W.cfg_plain16, "blocky128": W.cfg_blocky128}[args.config]()
     xi, c, err = tem.poles(wl.t, wl.degree)

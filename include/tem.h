@@ -168,6 +168,22 @@ int tem_set_conductivity(tem_ctx *ctx, const double *sigma, int flags);
 int tem_poles(int T, const double *t, const double *w, int degree, double tol,
               int J_max, int *J, double *xi, double *c, double *err);
 
+/* Single-time best approximation (Sec. 3.1): the type-[m/m] rational
+ * function r_m(x) = alpha0 + sum_i alpha_i / (x - xi_i) with the smallest
+ * uniform error to exp(-x) on x >= 0 (Halphen's 2 H^(-m-1/2) asymptotically,
+ * Sec. 3.3; Table 1's first column gives m for a tolerance).  m in [1, 32];
+ * beyond m = 14 the error stays at the FP64 floor (about 2e-14).  Outputs,
+ * for the J <= m poles kept (one per conjugate pair, with Im > 0, then the
+ * real poles: J = ceil(m/2) while the poles pair up, as they do up to
+ * m = 14), in host arrays of 2*m doubles the caller owns:
+ *   xi[2*J]   the poles xi_j (re, im) of r_m in the variable x = t lambda;
+ *   a[2*J]    the residues with the factor 2 of a pair folded in, so
+ *             r_m(x) = alpha0 + Re sum_j a_j / (x - xi_j);
+ *   alpha0    the constant term (r_m at infinity);
+ *   err       the uniform error (may be NULL).
+ * Host only; uses no device.  Returns TEM_EINVAL for m out of range. */
+int tem_poles_single(int m, int *J, double *xi, double *a, double *alpha0, double *err);
+
 /* Forward model (Sec. 3.2): for each of the n_src loops, solve the J shifted
  * complex-symmetric systems (K - xi_j M) x_j = f on the device and form
  *   data[(s*T + k)*n_rx + r] = dB_z/dt at receiver r, channel k   [T/s]  (host)
@@ -180,6 +196,30 @@ int tem_forward(tem_ctx *ctx, const tem_loop *src, int n_src,
                 const tem_receiver *rx, int n_rx, int T, int J,
                 const double *xi, const double *c, const tem_solve_opts *opts,
                 double *data, double *fields, tem_stats *stats);
+
+/* Single-time forward model (Sec. 3.1, eq. (rba)): for each of the n_src
+ * loops and every channel t_k, k < T (t[T] > 0, host),
+ *   u(t_k) = alpha0 b + Re sum_j a_j (t_k K - xi_j M)^-1 f,   b = M^-1 f,
+ * with (xi, a, alpha0, J) as produced by tem_poles_single (host arrays of
+ * 2*J doubles, J in [1, 32]).  Every channel has its own J shifted systems,
+ * (K + s M) x = f / t_k with s = -xi_j / t_k, J*T in all; they are solved by
+ * multi-shift sweeps of at most 64 shifts each, the shifts taken in order of
+ * |s| (one shared seed recurrence per sweep), and contracted with the
+ * coefficients a_j / t_k on the device.  Outputs as for tem_forward: data
+ * (host, may be NULL with n_rx = 0) and fields (device, NULL to skip) at
+ * fields[(s*T + k)*n_storage + e].  FP64 only: opts->precision and
+ * opts->method must be 0 and opts->keep_solutions 0 (TEM_EINVAL otherwise);
+ * rtol, max_iter, block and seed_shift apply to every sweep.  Device memory:
+ * (J*T + 1) complex vectors per concurrent source (up to 4).  stats: n_shifts
+ * = J*T; iterations = seed iterations of the last source summed over its
+ * sweeps; iters_per_shift[k], est_res[k] and true_res[k] hold, per channel k,
+ * the maxima over that channel's J systems.  No adjoint or Jacobian follows
+ * this call (they return TEM_ESTATE). */
+int tem_forward_single(tem_ctx *ctx, const tem_loop *src, int n_src,
+                       const tem_receiver *rx, int n_rx, int T, const double *t,
+                       int J, const double *xi, const double *a, double alpha0,
+                       const tem_solve_opts *opts, double *data, double *fields,
+                       tem_stats *stats);
 
 /* Adjoint (Sec. 4): given w[(s*T + k)*n_rx + r] = dphi/d data (host) for the
  * last tem_forward call, compute

@@ -163,21 +163,31 @@ def shifted_solve(prob, t: float, xi: complex, f: np.ndarray) -> np.ndarray:
     return spla.splu(A, permc_spec="MMD_AT_PLUS_A").solve(np.asarray(f, complex))
 
 
-def forward_single(prob, fit: dict, t, src: int = 0):
+def forward_single(prob, fit: dict, t, src: int = 0, terms: bool = False):
     """eq. (rba) for every channel t_k: u(t_k) = alpha_0 b + sum_i alpha_i
     (t_k K - xi_i M)^-1 f, the conjugate pole of a pair contributing the
     conjugate term (so the pair gives 2 Re).  Returns the fields U (n x K) and
-    the receiver data d (K x n_rx)."""
+    the receiver data d (K x n_rx); with terms, also S (K): the sum of the
+    M-norms of the terms, S_k = |alpha_0| ||b||_M + sum_i |alpha_i|
+    ||(t_k K - xi_i M)^-1 f||_M over all m poles (the scale of the rounding
+    in the sum)."""
     f = prob.F[:, src]
     b = f / prob.M
     t = np.atleast_1d(np.asarray(t, float))
     U = np.zeros((len(f), len(t)))
+    S = np.zeros(len(t))
+    mn = lambda v: float(np.sqrt(np.sum(prob.M * np.abs(v) ** 2)))
     for k, tk in enumerate(t):
         u = fit["alpha0"] * b
+        S[k] = abs(fit["alpha0"]) * mn(b)
         for p, a, pair in zip(fit["xi"], fit["alpha"], fit["pairs"]):
-            term = a * shifted_solve(prob, tk, p, f)
+            x = shifted_solve(prob, tk, p, f)
+            term = a * x
             u = u + (2 * term.real if pair else term.real)
+            S[k] += (2 if pair else 1) * abs(a) * mn(x)
         U[:, k] = u
+    if terms:
+        return U, (prob.Q @ U).T, S
     return U, (prob.Q @ U).T
 
 

@@ -89,6 +89,7 @@ struct DevBuf {
 // seed kernels of one solve are latency-bound, and concurrent solves fill the
 // device between each other's reduction boundaries.
 constexpr int kMaxConcurrentSolves = 4;
+constexpr int kMaxSinglePoles = 32;  // pole representatives of a single-time approximant
 
 // Workspace of one multi-shift solve.
 struct SolveSlot {
@@ -1787,6 +1788,185 @@ int tem_forward(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver
   return status;
 }
 
+int tem_forward_single(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_receiver* rx, int n_rx, int T,
+                       const double* t, int J, const double* xi, const double* a, double a0,
+                       const tem_solve_opts* opts, double* data, double* fields, tem_stats* stats) {
+  auto t_start = std::chrono::steady_clock::now();
+  if (!ctx) return fail(nullptr, TEM_EINVAL, "ctx is NULL");
+  ctx->fwd_valid = ctx->fwd_meta = false;  // no adjoint follows a single-time forward
+  if (!ctx->has_sigma) return fail(ctx, TEM_ESTATE, "conductivity not set");
+  int rc;
+  if ((rc = check_loops(ctx, src, n_src))) return rc;
+  if (n_rx < 0 || (n_rx > 0 && (!rx || !data))) return fail(ctx, TEM_EINVAL, "bad receiver arguments");
+  for (int r = 0; r < n_rx; ++r)
+    if (rx[r].i < 0 || rx[r].i >= ctx->nx || rx[r].j < 0 || rx[r].j >= ctx->ny)
+      return fail(ctx, TEM_EINVAL, "receiver " + std::to_string(r) + " outside the surface");
+  if (T < 1 || T > 64 || !t) return fail(ctx, TEM_EINVAL, "T must be in [1, 64] with t");
+  if (J < 1 || J > kMaxSinglePoles || !xi || !a) return fail(ctx, TEM_EINVAL, "J must be in [1, 32] with xi and a");
+  if (!std::isfinite(a0)) return fail(ctx, TEM_EINVAL, "non-finite alpha0");
+  for (int k = 0; k < T; ++k)
+    if (!(std::isfinite(t[k]) && t[k] > 0.0)) return fail(ctx, TEM_EINVAL, "channel times must be positive");
+  for (int j = 0; j < J; ++j) {
+    if (!std::isfinite(xi[2 * j]) || !std::isfinite(xi[2 * j + 1]) || !std::isfinite(a[2 * j]) ||
+        !std::isfinite(a[2 * j + 1]))
+      return fail(ctx, TEM_EINVAL, "non-finite pole or residue");
+    if (xi[2 * j] >= 0.0 && xi[2 * j + 1] == 0.0)
+      return fail(ctx, TEM_EINVAL, "a real pole on x >= 0 makes t K - xi M singular");
+  }
+  const tem_solve_opts o = resolve_opts(opts);
+  if (o.precision != 0 || o.method != 0 || o.keep_solutions)
+    return fail(ctx, TEM_EINVAL, "the single-time forward is FP64 (precision 0, method 0) and keeps no solutions");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  // the J T systems (t_k K - xi_j M) x = f = t_k (K + s M) x with s = -xi_j / t_k,
+  // ordered by |s| so that each multi-shift solve takes shifts of one scale
+  const int Jt = J * T;
+  std::vector<int> order(Jt);
+  std::vector<double> sre_all(Jt), sim_all(Jt);
+  for (int j = 0; j < J; ++j)
+    for (int k = 0; k < T; ++k) {
+      sre_all[j * T + k] = -xi[2 * j] / t[k];
+      sim_all[j * T + k] = -xi[2 * j + 1] / t[k];
+    }
+  for (int q = 0; q < Jt; ++q) order[q] = q;
+  std::stable_sort(order.begin(), order.end(), [&](int u, int v) {
+    return std::hypot(sre_all[u], sim_all[u]) < std::hypot(sre_all[v], sim_all[v]);
+  });
+  const int nch = (Jt + TEM_MAX_SHIFTS - 1) / TEM_MAX_SHIFTS;
+  const int per = (Jt + nch - 1) / nch;
+  // coefficients: column q (sorted position) of shift (j, k) feeds channel k
+  // with a_j / t_k; column Jt holds g = M^-1/2 f, so alpha0 b = alpha0 M^-1/2 g
+  // comes out of the same contraction
+  std::vector<double> Ch(2 * (size_t)(Jt + 1) * T, 0.0);
+  for (int q = 0; q < Jt; ++q) {
+    const int j = order[q] / T, k = order[q] % T;
+    Ch[2 * ((size_t)q * T + k)] = a[2 * j] / t[k];
+    Ch[2 * ((size_t)q * T + k) + 1] = a[2 * j + 1] / t[k];
+  }
+  for (int k = 0; k < T; ++k) Ch[2 * ((size_t)Jt * T + k)] = a0;
+  if ((rc = order_after_caller(ctx))) return rc;
+  hipStream_t st = ctx->work;
+  const size_t n3 = ctx->n3;
+  const int nconc = std::min(n_src, kMaxConcurrentSolves);
+  if ((int)ctx->Y.size() < nconc) ctx->Y.resize(nconc);
+  for (int i = 0; i < nconc; ++i)
+    if ((rc = ensure(ctx, ctx->Y[i], (size_t)(Jt + 1) * n3 * sizeof(double2)))) return rc;
+  if ((rc = ensure_slots(ctx, nconc))) return rc;
+  for (int i = 0; i < nconc; ++i)
+    if ((rc = ensure(ctx, ctx->slots[i].gvec, n3 * sizeof(double)))) return rc;
+  const int cpb = tem::cstencil_partials(ctx->g);
+  if ((rc = ensure(ctx, ctx->P, (size_t)TEM_MAX_SHIFTS * n3 * sizeof(double2))) ||
+      (rc = ensure(ctx, ctx->gc, n3 * sizeof(double2))) || (rc = ensure(ctx, ctx->f, n3 * sizeof(double))) ||
+      (rc = ensure(ctx, ctx->C, Ch.size() * sizeof(double))) ||
+      (rc = ensure(ctx, ctx->rx, 2 * (size_t)std::max(n_rx, 1) * sizeof(int))) ||
+      (rc = ensure(ctx, ctx->data, (size_t)T * std::max(n_rx, 1) * sizeof(double))) ||
+      (rc = ensure(ctx, ctx->sh, 4 * (size_t)TEM_MAX_SHIFTS * sizeof(double))) ||
+      (rc = ensure(ctx, ctx->cpart, (size_t)TEM_MAX_SHIFTS * cpb * sizeof(double))))
+    return rc;
+  HIPCHK(ctx, hipMemcpyAsync(ctx->C.p, Ch.data(), Ch.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  std::vector<int> rxi(2 * std::max(n_rx, 1), 0);
+  for (int r = 0; r < n_rx; ++r) {
+    rxi[2 * r] = rx[r].i;
+    rxi[2 * r + 1] = rx[r].j;
+  }
+  HIPCHK(ctx, hipMemcpyAsync(ctx->rx.p, rxi.data(), rxi.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  double* shd = (double*)ctx->sh.p;
+  tem_stats S{};
+  S.n_shifts = Jt;
+  S.converged = 1;
+  int status = TEM_OK;
+  std::vector<std::vector<double>> fs(nconc, std::vector<double>(n3));
+  std::vector<SolveState> states(nconc);
+  std::vector<double> true2(TEM_MAX_SHIFTS);
+  for (int s_first = 0; s_first < n_src; s_first += nconc) {
+    const int nb = std::min(nconc, n_src - s_first);
+    for (int i = 0; i < nb; ++i) {
+      loop_source(ctx, src[s_first + i], fs[i]);
+      HIPCHK(ctx, hipMemcpyAsync(ctx->f.p, fs[i].data(), n3 * sizeof(double), hipMemcpyHostToDevice, st));
+      tem::launch_scale(n3, ctx->d_dinv, (const double*)ctx->f.p, (double*)ctx->slots[i].gvec.p, st);
+      HIPCHK(ctx, hipGetLastError());
+    }
+    std::vector<int> its(nb, 0);
+    std::vector<double> worst_true(T, 0.0), worst_est(T, 0.0);
+    std::vector<int> worst_iters(T, 0);
+    for (int c0 = 0; c0 < Jt; c0 += per) {
+      const int Jc = std::min(per, Jt - c0);
+      std::vector<double> sre(Jc), sim(Jc);
+      for (int q = 0; q < Jc; ++q) {
+        sre[q] = sre_all[order[c0 + q]];
+        sim[q] = sim_all[order[c0 + q]];
+      }
+      double s0 = o.seed_shift;
+      if (!(s0 > 0.0)) {
+        double minre = 1e300, minabs = 1e300;
+        for (int q = 0; q < Jc; ++q) {
+          minre = std::min(minre, sre[q]);
+          minabs = std::min(minabs, std::hypot(sre[q], sim[q]));
+        }
+        s0 = std::max(minre, 1e-3 * minabs);
+      }
+      std::vector<double2*> ys(nb);
+      for (int i = 0; i < nb; ++i) ys[i] = (double2*)ctx->Y[i].p + (size_t)c0 * n3;
+      double secs = 0.0;
+      const int r = multishift_solve<double2>(ctx, sre, sim, s0, o, nb, ys.data(), states.data(), secs);
+      if (r == TEM_ENOCONV) {
+        S.converged = 0;
+        status = r;
+      } else if (r != TEM_OK) {
+        return r;
+      }
+      HIPCHK(ctx, hipMemcpyAsync(shd, sre.data(), Jc * sizeof(double), hipMemcpyHostToDevice, st));
+      HIPCHK(ctx, hipMemcpyAsync(shd + TEM_MAX_SHIFTS, sim.data(), Jc * sizeof(double), hipMemcpyHostToDevice, st));
+      for (int i = 0; i < nb; ++i) {
+        const SolveState& hs = states[i];
+        its[i] += hs.k;
+        // FP64 true residuals of this chunk's shifts
+        tem::launch_to_complex(n3, (const double*)ctx->slots[i].gvec.p, (double2*)ctx->gc.p, st);
+        tem::launch_cstencil(ctx->g, ys[i], n3, ctx->d_dinv, shd, shd + TEM_MAX_SHIFTS, Jc,
+                             (const double2*)ctx->gc.p, (double2*)ctx->P.p, n3, (double*)ctx->cpart.p, st);
+        tem::launch_reduce_rows((const double*)ctx->cpart.p, Jc, cpb, shd + 2 * TEM_MAX_SHIFTS, st);
+        HIPCHK(ctx, hipGetLastError());
+        HIPCHK(ctx, hipMemcpyAsync(true2.data(), shd + 2 * TEM_MAX_SHIFTS, Jc * sizeof(double),
+                                   hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+        for (int q = 0; q < Jc; ++q) {
+          const int k = order[c0 + q] % T;
+          worst_true[k] = std::max(worst_true[k], std::sqrt(true2[q] / hs.rr0));
+          worst_est[k] = std::max(worst_est[k], hs.est[q] / std::sqrt(hs.rr0));
+          worst_iters[k] = std::max(worst_iters[k], hs.iters[q]);
+          S.unknown_updates += (double)ctx->nunk * hs.iters[q];
+        }
+      }
+    }
+    for (int i = 0; i < nb; ++i) {
+      const int s = s_first + i;
+      double2* Y = (double2*)ctx->Y[i].p;
+      tem::launch_to_complex(n3, (const double*)ctx->slots[i].gvec.p, Y + (size_t)Jt * n3, st);
+      if (n_rx > 0) {
+        tem::launch_receivers(ctx->g, Y, Jt + 1, ctx->d_dinv, (const double*)ctx->C.p, T, (const int*)ctx->rx.p,
+                              n_rx, ctx->ks, (double*)ctx->data.p, st);
+        HIPCHK(ctx, hipGetLastError());
+        HIPCHK(ctx, hipMemcpyAsync(data + (size_t)s * T * n_rx, ctx->data.p, (size_t)T * n_rx * sizeof(double),
+                                   hipMemcpyDeviceToHost, st));
+      }
+      if (fields) {
+        tem::launch_contract(ctx->g, Y, Jt + 1, ctx->d_dinv, (const double*)ctx->C.p, T,
+                             fields + (size_t)s * T * ctx->nstore, st);
+        HIPCHK(ctx, hipGetLastError());
+      }
+      HIPCHK(ctx, hipStreamSynchronize(st));
+      S.iterations = its[i];
+    }
+    for (int k = 0; k < T; ++k) {
+      S.true_res[k] = worst_true[k];
+      S.est_res[k] = worst_est[k];
+      S.iters_per_shift[k] = worst_iters[k];
+    }
+  }
+  S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  if (stats) *stats = S;
+  return status;
+}
+
 int tem_solutions(tem_ctx* ctx, int s, double* X) {
   if (!ctx) return fail(nullptr, TEM_EINVAL, "ctx is NULL");
   if (!ctx->fwd_valid) return fail(ctx, TEM_ESTATE, "no stored solutions (run tem_forward with keep_solutions)");
@@ -2294,6 +2474,26 @@ int tem_poles(int T, const double* t, const double* w, int degree, double tol, i
   }
   if (err)
     for (int k = 0; k < T; ++k) err[k] = res.err[k];
+  return TEM_OK;
+}
+
+int tem_poles_single(int m, int* J, double* xi, double* a, double* alpha0, double* err) {
+  if (m < 1 || m > kMaxSinglePoles || !J || !xi || !a || !alpha0)
+    return fail(nullptr, TEM_EINVAL, "bad arguments to tem_poles_single (m must be in [1, 32])");
+  tem::SingleResult res;
+  std::string msg;
+  const int rc = tem::best_rational(m, res, msg);
+  if (rc != TEM_OK) return fail(nullptr, rc, msg);
+  const int nJ = (int)res.xi.size();
+  *J = nJ;
+  for (int j = 0; j < nJ; ++j) {
+    xi[2 * j] = res.xi[j].real();
+    xi[2 * j + 1] = res.xi[j].imag();
+    a[2 * j] = res.a[j].real();
+    a[2 * j + 1] = res.a[j].imag();
+  }
+  *alpha0 = res.a0;
+  if (err) *err = res.err;
   return TEM_OK;
 }
 

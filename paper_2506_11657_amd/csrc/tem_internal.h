@@ -255,5 +255,13 @@ struct RkfitResult {
 int rkfit(const std::vector<double>& t, const std::vector<double>& w, int degree, RkfitResult& out,
           std::string& msg);
 int table1_degree(double ratio, double tol);
+// single-time best approximation of exp(-x) of type [m/m] (Sec. 3.1)
+struct SingleResult {
+  std::vector<std::complex<double>> xi;  // ceil(m/2) poles (pairs with Im > 0, then real)
+  std::vector<std::complex<double>> a;   // residues, factor 2 folded for pairs
+  double a0 = 0.0;                       // constant term
+  double err = 0.0;                      // uniform error on [0, inf)
+};
+int best_rational(int m, SingleResult& out, std::string& msg);
 
 }  // namespace tem

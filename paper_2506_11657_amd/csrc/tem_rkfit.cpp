@@ -269,6 +269,77 @@ bool eigenvalues(Mat H, std::vector<cd>& ev) {
   return true;
 }
 
+// Rational Arnoldi on the diagonal surrogate x with the unit starting vector
+// v0 and the poles: orthonormal V (N x m+1) and the (m+1) x m pencil with
+// S V Kp = V Hp.  Step j solves (S - xi_j) w = v_j, orthogonalizes twice
+// (classical Gram-Schmidt) and normalizes; false on breakdown.
+bool rational_arnoldi(const std::vector<double>& x, const std::vector<double>& v0, const std::vector<cd>& poles,
+                      Mat& V, Mat& Kp, Mat& Hp) {
+  const int N = (int)x.size(), m = (int)poles.size();
+  V = Mat(N, m + 1);
+  Kp = Mat(m + 1, m);
+  Hp = Mat(m + 1, m);
+  for (int i = 0; i < N; ++i) V(i, 0) = v0[i];
+  std::vector<cd> wv(N), h(m + 1);
+  for (int j = 0; j < m; ++j) {
+    for (int i = 0; i < N; ++i) wv[i] = V(i, j) / (x[i] - poles[j]);
+    std::vector<cd> kc(j + 2, cd(0.0, 0.0));
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int l = 0; l <= j; ++l) {
+        cd d(0.0, 0.0);
+        const cd* vl = V.col(l);
+        for (int i = 0; i < N; ++i) d += std::conj(vl[i]) * wv[i];
+        h[l] = d;
+      }
+      for (int l = 0; l <= j; ++l) {
+        const cd* vl = V.col(l);
+        for (int i = 0; i < N; ++i) wv[i] -= h[l] * vl[i];
+        kc[l] += h[l];
+      }
+    }
+    kc[j + 1] = nrm2(wv.data(), N);
+    if (kc[j + 1] == cd(0.0, 0.0)) return false;
+    for (int i = 0; i < N; ++i) V(i, j + 1) = wv[i] / kc[j + 1];
+    for (int l = 0; l <= j + 1; ++l) {
+      Kp(l, j) = kc[l];
+      Hp(l, j) = poles[j] * kc[l];
+    }
+    Hp(j, j) += 1.0;
+  }
+  return true;
+}
+
+// RKFIT's new poles for the unit coefficient vector c: with the Householder
+// Q whose first column is c (up to a phase), the eigenvalues of the trailing
+// m x m part of the pencil (Q^* Hp, Q^* Kp).  False if the pencil is singular
+// or the QR iteration does not converge.
+bool relocated_poles(const Mat& Hp, const Mat& Kp, const std::vector<cd>& c, std::vector<cd>& z) {
+  const int m1 = (int)c.size(), m = m1 - 1;
+  std::vector<cd> u(c);
+  const cd ph = std::abs(c[0]) > 0 ? c[0] / std::abs(c[0]) : cd(1.0, 0.0);
+  u[0] += ph;  // u = c - alpha e1 with alpha = -ph (|c| = 1)
+  const double un = nrm2(u.data(), m1);
+  for (auto& e : u) e /= un;
+  auto reflect = [&](const Mat& P) {  // (I - 2 u u^*) P
+    Mat Q = P;
+    for (int j = 0; j < P.n; ++j) {
+      cd d(0.0, 0.0);
+      for (int i = 0; i < m1; ++i) d += std::conj(u[i]) * P(i, j);
+      d *= 2.0;
+      for (int i = 0; i < m1; ++i) Q(i, j) -= d * u[i];
+    }
+    return Q;
+  };
+  const Mat Ht = reflect(Hp), Kt = reflect(Kp);
+  Mat A(m, m), Bm(m, m);
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < m; ++i) {
+      A(i, j) = Ht(i + 1, j);
+      Bm(i, j) = Kt(i + 1, j);
+    }
+  return lu_solve(Bm, A) && eigenvalues(A, z);
+}
+
 struct Fit {
   std::vector<cd> reps;  // pairs (Im > 0) then real
   std::vector<cd> A;     // J x K residues (row j: A[j*K + k])
@@ -469,41 +540,17 @@ int rkfit(const std::vector<double>& t, const std::vector<double>& w, int m, Rkf
   for (int i = 0; i < np; ++i) poles.push_back(std::conj(poles[i]));
   if (m % 2) poles.push_back(cd(-1.0 / std::sqrt(tmin), 0.0));
 
+  const std::vector<double> v0(N, 1.0 / std::sqrt((double)N));  // v = ones, normalized
+
   double best_err = 1e300;
   Fit best;
   const int nth = std::max(1, std::min(8, (int)std::thread::hardware_concurrency()));
   for (int sweep = 0; sweep < 20; ++sweep) {
     // 1. rational Arnoldi
-    Mat V(N, m + 1), Kp(m + 1, m), Hp(m + 1, m);
-    for (int i = 0; i < N; ++i) V(i, 0) = 1.0 / std::sqrt((double)N);
-    std::vector<cd> wv(N), h(m + 1);
-    for (int j = 0; j < m; ++j) {
-      for (int i = 0; i < N; ++i) wv[i] = V(i, j) / (x[i] - poles[j]);
-      std::vector<cd> kc(j + 2, cd(0.0, 0.0));
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int l = 0; l <= j; ++l) {
-          cd d(0.0, 0.0);
-          const cd* vl = V.col(l);
-          for (int i = 0; i < N; ++i) d += std::conj(vl[i]) * wv[i];
-          h[l] = d;
-        }
-        for (int l = 0; l <= j; ++l) {
-          const cd* vl = V.col(l);
-          for (int i = 0; i < N; ++i) wv[i] -= h[l] * vl[i];
-          kc[l] += h[l];
-        }
-      }
-      kc[j + 1] = nrm2(wv.data(), N);
-      if (kc[j + 1] == cd(0.0, 0.0)) {
-        msg = "rational Arnoldi breakdown";
-        return TEM_EBREAKDOWN;
-      }
-      for (int i = 0; i < N; ++i) V(i, j + 1) = wv[i] / kc[j + 1];
-      for (int l = 0; l <= j + 1; ++l) {
-        Kp(l, j) = kc[l];
-        Hp(l, j) = poles[j] * kc[l];
-      }
-      Hp(j, j) += 1.0;
+    Mat V, Kp, Hp;
+    if (!rational_arnoldi(x, v0, poles, V, Kp, Hp)) {
+      msg = "rational Arnoldi breakdown";
+      return TEM_EBREAKDOWN;
     }
     // 2. stacked (I - V V^*) F_k V, reduced to R per thread (TSQR), then combined
     const int m1 = m + 1;
@@ -551,31 +598,9 @@ int rkfit(const std::vector<double>& t, const std::vector<double>& w, int m, Rkf
         for (int i = 0; i < m1; ++i) Stack(tid * m1 + i, j) = Rs[tid](i, j);
     const Mat R = householder_r(Stack);
     std::vector<cd> c = smallest_right_singular(R);
-    // 3. Householder Q with Q e1 = c / alpha, new poles from the trailing pencil
-    std::vector<cd> u(c);
-    const cd ph = std::abs(c[0]) > 0 ? c[0] / std::abs(c[0]) : cd(1.0, 0.0);
-    u[0] += ph;  // u = c - alpha e1 with alpha = -ph (|c| = 1)
-    const double un = nrm2(u.data(), m1);
-    for (auto& e : u) e /= un;
-    auto reflect = [&](const Mat& P) {  // (I - 2 u u^*) P
-      Mat Q = P;
-      for (int j = 0; j < P.n; ++j) {
-        cd d(0.0, 0.0);
-        for (int i = 0; i < m1; ++i) d += std::conj(u[i]) * P(i, j);
-        d *= 2.0;
-        for (int i = 0; i < m1; ++i) Q(i, j) -= d * u[i];
-      }
-      return Q;
-    };
-    const Mat Ht = reflect(Hp), Kt = reflect(Kp);
-    Mat A(m, m), Bm(m, m);
-    for (int j = 0; j < m; ++j)
-      for (int i = 0; i < m; ++i) {
-        A(i, j) = Ht(i + 1, j);
-        Bm(i, j) = Kt(i + 1, j);
-      }
+    // 3. new poles from the trailing pencil
     std::vector<cd> z;
-    if (!lu_solve(Bm, A) || !eigenvalues(A, z)) {
+    if (!relocated_poles(Hp, Kp, c, z)) {
       msg = "pole relocation failed (singular pencil or no QR convergence)";
       if (best.reps.empty()) return TEM_EBREAKDOWN;
       break;
@@ -608,6 +633,191 @@ int rkfit(const std::vector<double>& t, const std::vector<double>& w, int m, Rkf
     const double f = best.reps[j].imag() > 0 ? 2.0 : 1.0;
     for (int k = 0; k < K; ++k) out.c[(size_t)j * K + k] = f * best.A[(size_t)j * K + k] / tmax;
   }
+  return TEM_OK;
+}
+
+// Single-time best approximation (Sec. 3.1): the type-[m/m] function
+//   r(x) = a0 + sum_i alpha_i / (x - xi_i)  ~  exp(-x)  on [0, inf)
+// with the smallest uniform error.  The paper takes it from the literature
+// without a method; here RKFIT relocates the poles on the one channel t = 1
+// with a constant term in the residue fit, and Lawson's iteratively
+// reweighted least squares turns the least-squares fit into the minimax one:
+// after 5 unweighted sweeps, every sweep multiplies the sample weights by
+// |error|^(1/2) (normalized to max 1) and relocates in the weighted inner
+// product (starting vector sqrt(w)).  80 sweeps; the one with the smallest
+// uniform error is kept.  Samples: 0 and 9 (1 + s)/(1 - s) at Chebyshev
+// points s = -cos(pi l / 1999) < 1.
+namespace {
+
+// weighted least-squares a0 and residues (pairs: one complex residue, real
+// poles: a real one) over the constant and {1/(x - p)}
+void fit_with_constant(const std::vector<cd>& reps, const std::vector<double>& x, const std::vector<double>& y,
+                       const std::vector<double>& w, double& a0, std::vector<cd>& alpha) {
+  const int N = (int)x.size();
+  int ncol = 1;
+  for (const cd& p : reps) ncol += p.imag() > 0 ? 2 : 1;
+  Mat B(N, ncol + 1);
+  std::vector<double> sw(N);
+  for (int i = 0; i < N; ++i) sw[i] = std::sqrt(w[i]);
+  for (int i = 0; i < N; ++i) B(i, 0) = sw[i];
+  int col = 1;
+  for (const cd& p : reps) {
+    for (int i = 0; i < N; ++i) {
+      const cd g = 1.0 / (x[i] - p);
+      if (p.imag() > 0) {
+        B(i, col) = sw[i] * 2.0 * g.real();
+        B(i, col + 1) = -sw[i] * 2.0 * g.imag();
+      } else {
+        B(i, col) = sw[i] * g.real();
+      }
+    }
+    col += p.imag() > 0 ? 2 : 1;
+  }
+  std::vector<double> scale(ncol);
+  for (int j = 0; j < ncol; ++j) {
+    scale[j] = nrm2(B.col(j), N);
+    if (scale[j] == 0.0) scale[j] = 1.0;
+    for (int i = 0; i < N; ++i) B(i, j) /= scale[j];
+  }
+  for (int i = 0; i < N; ++i) B(i, ncol) = sw[i] * y[i];
+  const Mat R = householder_r(B);
+  std::vector<double> coef(ncol);
+  for (int i = ncol - 1; i >= 0; --i) {
+    double s = R(i, ncol).real();
+    for (int l = i + 1; l < ncol; ++l) s -= R(i, l).real() * coef[l];
+    const double d = R(i, i).real();
+    coef[i] = d != 0.0 ? s / d : 0.0;
+  }
+  for (int j = 0; j < ncol; ++j) coef[j] /= scale[j];
+  a0 = coef[0];
+  alpha.assign(reps.size(), cd(0.0, 0.0));
+  int r = 1;
+  for (size_t j = 0; j < reps.size(); ++j) {
+    if (reps[j].imag() > 0) {
+      alpha[j] = cd(coef[r], coef[r + 1]);
+      r += 2;
+    } else {
+      alpha[j] = cd(coef[r], 0.0);
+      r += 1;
+    }
+  }
+}
+
+double eval_single(const std::vector<cd>& reps, const std::vector<cd>& alpha, double a0, double x) {
+  double r = a0;
+  for (size_t j = 0; j < reps.size(); ++j) {
+    const double v = (alpha[j] / (x - reps[j])).real();
+    r += reps[j].imag() > 0 ? 2.0 * v : v;
+  }
+  return r;
+}
+
+// max |exp(-x) - r(x)| over 0, npts log-spaced points on [1e-6, 1e8] and
+// x = infinity (where r = a0)
+double single_error(const std::vector<cd>& reps, const std::vector<cd>& alpha, double a0, int npts) {
+  const int nth = std::max(1, std::min(8, (int)std::thread::hardware_concurrency()));
+  std::vector<double> part(nth, 0.0);
+  auto work = [&](int t) {
+    for (int i = t; i <= npts; i += nth) {
+      const double x = i == 0 ? 0.0 : std::pow(10.0, -6.0 + 14.0 * (i - 1) / (npts - 1));
+      part[t] = std::max(part[t], std::abs(std::exp(-x) - eval_single(reps, alpha, a0, x)));
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nth; ++t) th.emplace_back(work, t);
+  work(0);
+  for (auto& t : th) t.join();
+  double e = std::abs(a0);
+  for (double p : part) e = std::max(e, p);
+  return e;
+}
+
+}  // namespace
+
+int best_rational(int m, SingleResult& out, std::string& msg) {
+  std::vector<double> x{0.0};
+  const int ns = 2000;
+  for (int l = 1; l < ns; ++l) {
+    const double s = -std::cos(M_PI * l / (ns - 1));
+    if (s < 1.0) x.push_back(9.0 * (1.0 + s) / (1.0 - s));
+  }
+  const int N = (int)x.size();
+  std::vector<double> y(N), w(N, 1.0), v0(N);
+  for (int i = 0; i < N; ++i) y[i] = std::exp(-x[i]);
+  std::vector<cd> poles;
+  for (int i = 0; i < m / 2; ++i) poles.push_back(-std::exp(cd(0.0, M_PI / 3)));
+  for (int i = 0; i < m / 2; ++i) poles.push_back(-std::exp(cd(0.0, -M_PI / 3)));
+  if (m % 2) poles.push_back(cd(-1.0, 0.0));
+  const int m1 = m + 1;
+  double best_err = 1e300, best_a0 = 0.0;
+  std::vector<cd> best_reps, best_alpha;
+  for (int sweep = 0; sweep < 80; ++sweep) {
+    double vn = 0.0;
+    for (int i = 0; i < N; ++i) vn += w[i];
+    vn = std::sqrt(vn);
+    for (int i = 0; i < N; ++i) v0[i] = std::sqrt(w[i]) / vn;
+    Mat V, Kp, Hp;
+    if (!rational_arnoldi(x, v0, poles, V, Kp, Hp)) {
+      msg = "rational Arnoldi breakdown";
+      if (best_reps.empty()) return TEM_EBREAKDOWN;
+      break;
+    }
+    // (I - V V^*) F V with F = diag(exp(-x))
+    Mat L(N, m1);
+    for (int j = 0; j < m1; ++j)
+      for (int i = 0; i < N; ++i) L(i, j) = y[i] * V(i, j);
+    Mat G(m1, m1);
+    for (int j = 0; j < m1; ++j)
+      for (int l = 0; l < m1; ++l) {
+        cd d(0.0, 0.0);
+        for (int i = 0; i < N; ++i) d += std::conj(V(i, l)) * L(i, j);
+        G(l, j) = d;
+      }
+    for (int j = 0; j < m1; ++j)
+      for (int i = 0; i < N; ++i) {
+        cd s = L(i, j);
+        for (int l = 0; l < m1; ++l) s -= V(i, l) * G(l, j);
+        L(i, j) = s;
+      }
+    const std::vector<cd> c = smallest_right_singular(householder_r(L));
+    std::vector<cd> z;
+    if (!relocated_poles(Hp, Kp, c, z)) {
+      msg = "pole relocation failed (singular pencil or no QR convergence)";
+      if (best_reps.empty()) return TEM_EBREAKDOWN;
+      break;
+    }
+    poles = symmetrize(z, poles);
+    const std::vector<cd> reps = representatives(poles);
+    double a0;
+    std::vector<cd> alpha;
+    fit_with_constant(reps, x, y, w, a0, alpha);
+    const double e = single_error(reps, alpha, a0, 4000);
+    if (std::isfinite(e) && e < best_err) {
+      best_err = e;
+      best_reps = reps;
+      best_alpha = alpha;
+      best_a0 = a0;
+    }
+    if (sweep + 1 >= 5) {  // Lawson step
+      double wmax = 0.0;
+      for (int i = 0; i < N; ++i) {
+        const double ei = std::abs(y[i] - eval_single(reps, alpha, a0, x[i]));
+        w[i] *= std::sqrt(ei);
+        wmax = std::max(wmax, w[i]);
+      }
+      if (!(wmax > 0.0) || !std::isfinite(wmax)) break;
+      for (int i = 0; i < N; ++i) w[i] = std::max(w[i] / wmax, 1e-300);
+    }
+  }
+  if (best_reps.empty()) {
+    msg = "no finite single-time fit";
+    return TEM_EBREAKDOWN;
+  }
+  out.xi = best_reps;
+  out.a.resize(best_reps.size());
+  for (size_t j = 0; j < best_reps.size(); ++j) out.a[j] = (best_reps[j].imag() > 0 ? 2.0 : 1.0) * best_alpha[j];
+  out.a0 = best_a0;
+  out.err = single_error(best_reps, best_alpha, best_a0, 200000);
   return TEM_OK;
 }
 

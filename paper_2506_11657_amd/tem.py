@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "TEM_OK", -1: "TEM_EINVAL", -2: "TEM_ENOMEM", -3: "TEM_ENOCON
 EXPORTS = ["tem_setup_grid", "tem_set_conductivity", "tem_poles", "tem_forward", "tem_adjoint",
            "tem_solutions", "tem_apply", "tem_apply_noalloc", "tem_sizes", "tem_destroy", "tem_last_error",
            "tem_engine_create", "tem_attach_engine", "tem_engine_stats", "tem_engine_destroy",
-           "tem_jacobian_apply"]
+           "tem_jacobian_apply", "tem_poles_single", "tem_forward_single"]
 
 
 class tem_loop(C.Structure):
@@ -82,6 +82,10 @@ def lib():
         L.tem_forward.argtypes = [C.c_void_p, C.POINTER(tem_loop), C.c_int, C.POINTER(tem_receiver), C.c_int,
                                   C.c_int, C.c_int, dp, dp, C.POINTER(tem_solve_opts), dp, C.c_void_p,
                                   C.POINTER(tem_stats)]
+        L.tem_poles_single.argtypes = [C.c_int, ip, dp, dp, dp, dp]
+        L.tem_forward_single.argtypes = [C.c_void_p, C.POINTER(tem_loop), C.c_int, C.POINTER(tem_receiver),
+                                         C.c_int, C.c_int, dp, C.c_int, dp, dp, C.c_double,
+                                         C.POINTER(tem_solve_opts), dp, C.c_void_p, C.POINTER(tem_stats)]
         L.tem_adjoint.argtypes = [C.c_void_p, dp, dp, C.POINTER(tem_stats)]
         L.tem_jacobian_apply.argtypes = [C.c_void_p, dp, dp, C.POINTER(tem_stats)]
         L.tem_solutions.argtypes = [C.c_void_p, C.c_int, dp]
@@ -135,6 +139,20 @@ def poles(t, degree=0, tol=1e-8, w=None, j_max=TEM_MAX_SHIFTS):
     xi_c = xi[:2 * J].view(np.complex128).copy()
     c_c = c[:2 * J * T].view(np.complex128).reshape(J, T).copy()
     return xi_c, c_c, err
+
+
+def poles_single(m):
+    """tem_poles_single: the type-[m/m] best approximation of exp(-x) on
+    [0, inf): poles xi (ceil(m/2) complex, one per pair), residues a (factor
+    2 of pairs folded in), the constant alpha0 and the uniform error."""
+    J = C.c_int(0)
+    xi = np.zeros(2 * 32)
+    a = np.zeros(2 * 32)
+    a0 = C.c_double(0.0)
+    err = C.c_double(0.0)
+    _check(lib().tem_poles_single(int(m), C.byref(J), _dptr(xi), _dptr(a), C.byref(a0), C.byref(err)))
+    J = J.value
+    return xi[:2 * J].view(np.complex128).copy(), a[:2 * J].view(np.complex128).copy(), a0.value, err.value
 
 
 class Engine:
@@ -262,6 +280,44 @@ class Context:
         _check(status, self._h, allow=(TEM_ENOCONV,) if allow_noconv else ())
         self._n_src = len(loops)
         self._T, self._n_rx = T, n_rx
+        out = st.as_dict()
+        out["status"] = STATUS_NAMES[status]
+        return data[:, :, :n_rx], out
+
+    def forward_single(self, loops, receivers, t, xi, a, alpha0, fields=None, rtol=0.0, max_iter=0, block=0,
+                       seed_shift=0.0, allow_noconv=False, profile=False):
+        """tem_forward_single: eq. (rba) for every channel t (T) with the
+        single-time approximant (xi, a, alpha0) of poles_single.  fields:
+        optional device tensor (n_src, T, n_storage) float64.  Returns (data
+        (n_src, T, n_rx), stats dict)."""
+        src = (tem_loop * len(loops))()
+        for s, L in enumerate(loops):
+            v = (L.i0, L.i1, L.j0, L.j1, L.current) if hasattr(L, "i0") else tuple(L)
+            src[s] = tem_loop(int(v[0]), int(v[1]), int(v[2]), int(v[3]), float(v[4]))
+        n_rx = len(receivers)
+        rx = (tem_receiver * max(n_rx, 1))()
+        for r, (i, j) in enumerate(receivers):
+            rx[r] = tem_receiver(int(i), int(j))
+        t = _f64(t)
+        T = len(t)
+        xi = np.ascontiguousarray(np.asarray(xi, np.complex128))
+        a = np.ascontiguousarray(np.asarray(a, np.complex128))
+        if xi.shape != a.shape or xi.ndim != 1:
+            raise ValueError("xi and a must be 1-D with one residue per pole")
+        data = np.zeros((len(loops), T, max(n_rx, 1)))
+        fptr = None
+        if fields is not None:
+            if tuple(fields.shape) != (len(loops), T, self.n_storage) or not fields.is_cuda:
+                raise ValueError("fields must be a device tensor of shape (n_src, T, n_storage)")
+            fptr = C.c_void_p(fields.data_ptr())
+        opts = tem_solve_opts(0, float(rtol), int(max_iter), int(block), float(seed_shift), 0, 0,
+                              1 if profile else 0, 0)
+        st = tem_stats()
+        self.generation += 1
+        status = lib().tem_forward_single(self._h, src, len(loops), rx, n_rx, T, _dptr(t), len(xi),
+                                          _dptr(xi.view(np.float64)), _dptr(a.view(np.float64)), float(alpha0),
+                                          C.byref(opts), _dptr(data), fptr, C.byref(st))
+        _check(status, self._h, allow=(TEM_ENOCONV,) if allow_noconv else ())
         out = st.as_dict()
         out["status"] = STATUS_NAMES[status]
         return data[:, :, :n_rx], out

@@ -107,3 +107,39 @@ def test_bench_refuses_more_than_one_gpu():
     p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
                        timeout=120)
     assert p.returncode == 2 and "one GPU" in p.stderr
+
+
+@pytest.mark.parametrize("tol,m", list(zip(TABLE["tolerances"], TABLE["degree"]["1"])))
+def test_host_single_time_table1(tol, m):
+    """tem_poles_single meets Table 1's t_max/t_min = 1 column: degree m
+    reaches tol and m - 1 does not."""
+    assert T.poles_single(m)[3] <= tol
+    assert T.poles_single(m - 1)[3] > tol
+
+
+def test_host_single_time_best_and_counts():
+    """The host fit is the best approximation: its uniform error agrees with
+    the oracle's (itself pinned by equioscillation) and lies just below
+    Halphen's 2 H^(-m-1/2); conjugate pairs give the 124 and 217 solve counts
+    of Sec. 3.1 and 5.1; invalid degrees are refused."""
+    from oracle import rkfit, single
+    for m in (2, 5, 8, 10):
+        xi, a, a0, err = T.poles_single(m)
+        fit = {"xi": xi, "alpha": np.where(xi.imag > 0, 0.5, 1.0) * a, "alpha0": a0}
+        assert abs(single.uniform_error(fit) - err) <= 1e-6 * err
+        assert abs(err - single.best_rational(m)["err"]) <= 1e-3 * err
+        assert 0.95 <= err / (2 * rkfit.HALPHEN ** (-m - 0.5)) <= 1.0
+        assert np.all((xi.imag > 0) | (xi.real < 0))
+    assert 31 * len(T.poles_single(7)[0]) == COUNTS["single_time_m7_K31_solves"]
+    assert 31 * len(T.poles_single(14)[0]) == COUNTS["single_time_m14_K31_solves"]
+    for m in (0, 33):
+        with pytest.raises(T.TemError):
+            T.poles_single(m)
+
+
+def test_forward_single_validation_without_gpu():
+    import ctypes as C
+    L = T.lib()
+    z = np.zeros(4)
+    p = z.ctypes.data_as(C.POINTER(C.c_double))
+    assert L.tem_forward_single(None, None, 0, None, 0, 1, p, 1, p, p, 0.0, None, None, None, None) == T.TEM_EINVAL

@@ -1,0 +1,108 @@
+"""GPU parity of the single-time forward (Sec. 3.1, eq. (rba)) against the
+oracle's direct solves of t_k K - xi_i M, with the oracle's best-approximation
+poles and residues on both sides.
+
+Bar: per channel ||u_gpu(t_k) - u_or(t_k)||_M <= 1e-8 ||u_or(t_k)||_M + eta S_k
+and |d_gpu - d_or| <= 1e-8 |d_or| + eta ||q||_{M^-1} S_k, where S_k is the sum of
+the M-norms of the terms of eq. (rba) (the oracle's ``terms``) and eta = 1e-9.
+That is ten times below the contract's per-solve bar of 1e-8 (which bounds
+the channel error by 1e-8 S_k) and 18x above the oracle's own floor on these
+grids: its sparse-LU and banded-LU evaluations agree to 3.0e-11 S_k (m = 14,
+10^3) and 5.5e-11 S_k (m = 7, 8^3).  Every channel here is dominated by
+cancellation in the residue sum (S_k / ||u_k||_M from 20 to 2e11: the
+best-approximation residues are large), so no channel is held to a relative
+bar alone.
+"""
+import numpy as np
+import pytest
+
+import tem_workloads as W
+from oracle import direct, single, yee
+
+pytestmark = pytest.mark.gpu
+
+ETA = 1e-9
+
+
+@pytest.fixture(scope="module")
+def tem():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_11657_amd import tem as T
+    T.lib()
+    return T
+
+
+def _device_args(fit):
+    return fit["xi"], np.where(fit["pairs"], 2.0, 1.0) * fit["alpha"], fit["alpha0"]
+
+
+def _check(P, U, d, Uo, do, S):
+    eu = direct.m_norm(P, U - Uo)
+    un = direct.m_norm(P, Uo)
+    assert np.all(eu <= 1e-8 * un + ETA * S), (eu / S).max()
+    qn = np.sqrt(np.asarray(P.Q.multiply(P.Q) @ (1.0 / P.M)).ravel())
+    ed = np.abs(d - do)
+    assert np.all(ed <= 1e-8 * np.abs(do) + ETA * np.outer(S, qn)), (ed / np.outer(S, qn)).max()
+    return (eu / S).max()
+
+
+def test_single_time_parity_two_sources_fields(tem):
+    """m = 14 (the paper's degree, 7 conjugate pairs) at 10 channels: 70
+    shifted systems in two multi-shift sweeps of 35, two loops, fields and
+    receivers."""
+    import torch
+    wl = W.small_case(10, seed=5, t=W.log_channels(1e-5, 1e-2, 10))
+    wl.loops = [W.Loop(1, 9, 1, 9, 1.0), W.Loop(2, 6, 3, 8, 0.5)]
+    wl.receivers = [(5, 5), (3, 7), (8, 2)]
+    P = yee.Problem(wl)
+    fit = single.best_rational(14)
+    xi, a, a0 = _device_args(fit)
+    ctx = tem.Context.from_workload(wl)
+    T = len(wl.t)
+    fields = torch.zeros((2, T, ctx.n_storage), dtype=torch.float64, device="cuda")
+    data, st = ctx.forward_single(wl.loops, wl.receivers, wl.t, xi, a, a0, fields=fields, rtol=1e-12)
+    assert st["converged"] and st["n_shifts"] == 7 * T
+    F = fields.cpu().numpy()
+    worst = 0.0
+    for s in range(2):
+        Uo, do, S = single.forward_single(P, fit, wl.t, src=s, terms=True)
+        U = F[s][:, P.idx].T
+        assert np.abs(F[s][:, ~P.mask]).max() == 0.0
+        worst = max(worst, _check(P, U, data[s], Uo, do, S))
+    print("seed iterations (last source, both sweeps)", st["iterations"], "max channel error / S_k %.2e" % worst,
+          "max true residual %.2e" % max(st["true_res"][:T]))
+    assert max(st["true_res"][:T]) <= 1e-8
+
+
+def test_single_time_odd_degree_real_pole(tem):
+    """m = 7 (Table 1's degree for 1e-6): three pairs and one real pole, 20
+    channels, 80 systems in two sweeps of 40, receivers only."""
+    wl = W.small_case(8, seed=6, t=W.log_channels(1e-5, 1e-2, 20))
+    wl.receivers = [(4, 4), (2, 5)]
+    P = yee.Problem(wl)
+    fit = single.best_rational(7)
+    assert fit["pairs"].sum() == 3 and len(fit["xi"]) == 4
+    xi, a, a0 = _device_args(fit)
+    ctx = tem.Context.from_workload(wl)
+    data, st = ctx.forward_single(wl.loops, wl.receivers, wl.t, xi, a, a0, rtol=1e-12)
+    assert st["converged"] and st["n_shifts"] == 80
+    Uo, do, S = single.forward_single(P, fit, wl.t, terms=True)
+    qn = np.sqrt(np.asarray(P.Q.multiply(P.Q) @ (1.0 / P.M)).ravel())
+    ed = np.abs(data[0] - do)
+    assert np.all(ed <= 1e-8 * np.abs(do) + ETA * np.outer(S, qn)), (ed / np.outer(S, qn)).max()
+
+
+def test_single_time_validation_and_no_adjoint(tem):
+    """A non-finite alpha0 is refused; no adjoint follows a single-time forward."""
+    wl = W.small_case(6, seed=1, t=W.log_channels(1e-5, 1e-3, 3))
+    fit = single.best_rational(4)
+    xi, a, a0 = _device_args(fit)
+    ctx = tem.Context.from_workload(wl)
+    data, st = ctx.forward_single(wl.loops, wl.receivers, wl.t, xi, a, a0, rtol=1e-10)
+    assert st["converged"]
+    with pytest.raises(tem.TemError):
+        ctx.adjoint(np.ones((1, 3, len(wl.receivers))))
+    with pytest.raises(tem.TemError):
+        ctx.forward_single(wl.loops, wl.receivers, wl.t, xi, a, np.nan)
