@@ -312,7 +312,7 @@ def single_time_bench(args):
     xi, c, err = tem.poles(wl.t, wl.degree)
     out = {"workload": wl.name, "channels": T}
     runs = {}
-    for name in ("shared", "single"):
+    for name in (("single",) if args.single_only else ("shared", "single")):
         for rep in range(2):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -330,11 +330,12 @@ def single_time_bench(args):
                      "max_true_res": float(max(st["true_res"][:min(64, T)]))}
     out["single"]["degree"] = args.single_degree
     out["single"]["uniform_error"] = err_single
-    out["shared"]["degree"] = wl.degree
-    out["shared"]["max_channel_error"] = float(err.max())
-    out["time_ratio_single_over_shared"] = out["single"]["seconds"] / out["shared"]["seconds"]
-    rel = np.abs(runs["single"] - runs["shared"]) / np.abs(runs["shared"])
-    out["dbz_dt_rel_dev"] = [float(v) for v in rel]
+    if not args.single_only:
+        out["shared"]["degree"] = wl.degree
+        out["shared"]["max_channel_error"] = float(err.max())
+        out["time_ratio_single_over_shared"] = out["single"]["seconds"] / out["shared"]["seconds"]
+        rel = np.abs(runs["single"] - runs["shared"]) / np.abs(runs["shared"])
+        out["dbz_dt_rel_dev"] = [float(v) for v in rel]
     ctx.close()
     print(json.dumps({"single_time": out}), flush=True)
 
@@ -377,6 +378,7 @@ def main():
     ap.add_argument("--single-time", action="store_true",
                     help="compare the single-time baseline (Sec. 3.1) with the shared-pole forward")
     ap.add_argument("--single-degree", type=int, default=14)
+    ap.add_argument("--single-only", action="store_true", help="--single-time: skip the shared-pole forwards")
     ap.add_argument("--serve-max-active", type=int, default=4)
     ap.add_argument("--serve-first", type=int, default=0,
                     help="serve requests serve_first .. serve_first + serve - 1 of the trace")
