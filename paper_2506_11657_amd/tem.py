@@ -319,6 +319,9 @@ class Context:
                                           C.byref(opts), _dptr(data), fptr, C.byref(st))
         _check(status, self._h, allow=(TEM_ENOCONV,) if allow_noconv else ())
         out = st.as_dict()
+        # per channel: the maxima over that channel's systems
+        for key in ("iters_per_shift", "est_res", "true_res"):
+            out[key] = out[key][:T]
         out["status"] = STATUS_NAMES[status]
         return data[:, :, :n_rx], out
 

@@ -63,7 +63,7 @@ def test_single_time_parity_two_sources_fields(tem):
     T = len(wl.t)
     fields = torch.zeros((2, T, ctx.n_storage), dtype=torch.float64, device="cuda")
     data, st = ctx.forward_single(wl.loops, wl.receivers, wl.t, xi, a, a0, fields=fields, rtol=1e-12)
-    assert st["converged"] and st["n_shifts"] == 7 * T
+    assert st["converged"] and st["n_shifts"] == 7 * T and len(st["true_res"]) == T
     F = fields.cpu().numpy()
     worst = 0.0
     for s in range(2):
