@@ -1877,6 +1877,8 @@ int tem_forward_single(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_r
   std::vector<std::vector<double>> fs(nconc, std::vector<double>(n3));
   std::vector<SolveState> states(nconc);
   std::vector<double> true2(TEM_MAX_SHIFTS);
+  std::vector<double> worst_true(T, 0.0), worst_est(T, 0.0);  // per channel, over sources and poles
+  std::vector<int> worst_iters(T, 0);
   for (int s_first = 0; s_first < n_src; s_first += nconc) {
     const int nb = std::min(nconc, n_src - s_first);
     for (int i = 0; i < nb; ++i) {
@@ -1886,8 +1888,6 @@ int tem_forward_single(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_r
       HIPCHK(ctx, hipGetLastError());
     }
     std::vector<int> its(nb, 0);
-    std::vector<double> worst_true(T, 0.0), worst_est(T, 0.0);
-    std::vector<int> worst_iters(T, 0);
     for (int c0 = 0; c0 < Jt; c0 += per) {
       const int Jc = std::min(per, Jt - c0);
       std::vector<double> sre(Jc), sim(Jc);
