@@ -202,10 +202,11 @@ int tem_forward(tem_ctx *ctx, const tem_loop *src, int n_src,
  *   u(t_k) = alpha0 b + Re sum_j a_j (t_k K - xi_j M)^-1 f,   b = M^-1 f,
  * with (xi, a, alpha0, J) as produced by tem_poles_single (host arrays of
  * 2*J doubles, J in [1, 32]).  Every channel has its own J shifted systems,
- * (K + s M) x = f / t_k with s = -xi_j / t_k, J*T in all; they are solved by
- * multi-shift sweeps of at most 64 shifts each, the shifts taken in order of
- * |s| (one shared seed recurrence per sweep), and contracted with the
- * coefficients a_j / t_k on the device.  Outputs as for tem_forward: data
+ * (K + s M) x = f / t_k with s = -xi_j / t_k, J*T in all; they share one
+ * multi-shift seed recurrence when J*T <= 320, else they are sorted by |s|
+ * and cut into equal sweeps of at most 320 shifts (64 when the context is
+ * attached to a solve engine), and they are contracted with the coefficients
+ * a_j / t_k on the device.  Outputs as for tem_forward: data
  * (host, may be NULL with n_rx = 0) and fields (device, NULL to skip) at
  * fields[(s*T + k)*n_storage + e].  FP64 only: opts->precision and
  * opts->method must be 0 and opts->keep_solutions 0 (TEM_EINVAL otherwise);

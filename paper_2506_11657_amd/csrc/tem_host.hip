@@ -24,7 +24,7 @@
 using tem::GridArgs;
 using tem::SolveState;
 // the pinned head buffer holds two heads (two solver blocks in flight)
-constexpr size_t kHeadStride = 2048;
+constexpr size_t kHeadStride = 4096;
 static_assert(sizeof(tem::SolveHead) <= kHeadStride, "pinned head buffer");
 
 // Device memory of tem_apply_noalloc: a fixed array in the code object, one
@@ -1818,7 +1818,9 @@ int tem_forward_single(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_r
     return fail(ctx, TEM_EINVAL, "the single-time forward is FP64 (precision 0, method 0) and keeps no solutions");
   HIPCHK(ctx, hipSetDevice(ctx->device));
   // the J T systems (t_k K - xi_j M) x = f = t_k (K + s M) x with s = -xi_j / t_k,
-  // ordered by |s| so that each multi-shift solve takes shifts of one scale
+  // all on one shared seed recurrence when they fit one solve (kMaxShifts),
+  // else ordered by |s| and cut into equal sweeps, each taking shifts of one
+  // scale (sweeps routed to a solve engine take at most 64)
   const int Jt = J * T;
   std::vector<int> order(Jt);
   std::vector<double> sre_all(Jt), sim_all(Jt);
@@ -1831,7 +1833,8 @@ int tem_forward_single(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_r
   std::stable_sort(order.begin(), order.end(), [&](int u, int v) {
     return std::hypot(sre_all[u], sim_all[u]) < std::hypot(sre_all[v], sim_all[v]);
   });
-  const int nch = (Jt + TEM_MAX_SHIFTS - 1) / TEM_MAX_SHIFTS;
+  const int cap = uses_engine(ctx) ? TEM_MAX_SHIFTS : tem::kMaxShifts;
+  const int nch = (Jt + cap - 1) / cap;
   const int per = (Jt + nch - 1) / nch;
   // coefficients: column q (sorted position) of shift (j, k) feeds channel k
   // with a_j / t_k; column Jt holds g = M^-1/2 f, so alpha0 b = alpha0 M^-1/2 g
@@ -1914,26 +1917,30 @@ int tem_forward_single(tem_ctx* ctx, const tem_loop* src, int n_src, const tem_r
       } else if (r != TEM_OK) {
         return r;
       }
-      HIPCHK(ctx, hipMemcpyAsync(shd, sre.data(), Jc * sizeof(double), hipMemcpyHostToDevice, st));
-      HIPCHK(ctx, hipMemcpyAsync(shd + TEM_MAX_SHIFTS, sim.data(), Jc * sizeof(double), hipMemcpyHostToDevice, st));
       for (int i = 0; i < nb; ++i) {
         const SolveState& hs = states[i];
         its[i] += hs.k;
-        // FP64 true residuals of this chunk's shifts
         tem::launch_to_complex(n3, (const double*)ctx->slots[i].gvec.p, (double2*)ctx->gc.p, st);
-        tem::launch_cstencil(ctx->g, ys[i], n3, ctx->d_dinv, shd, shd + TEM_MAX_SHIFTS, Jc,
-                             (const double2*)ctx->gc.p, (double2*)ctx->P.p, n3, (double*)ctx->cpart.p, st);
-        tem::launch_reduce_rows((const double*)ctx->cpart.p, Jc, cpb, shd + 2 * TEM_MAX_SHIFTS, st);
-        HIPCHK(ctx, hipGetLastError());
-        HIPCHK(ctx, hipMemcpyAsync(true2.data(), shd + 2 * TEM_MAX_SHIFTS, Jc * sizeof(double),
-                                   hipMemcpyDeviceToHost, st));
-        HIPCHK(ctx, hipStreamSynchronize(st));
-        for (int q = 0; q < Jc; ++q) {
-          const int k = order[c0 + q] % T;
-          worst_true[k] = std::max(worst_true[k], std::sqrt(true2[q] / hs.rr0));
-          worst_est[k] = std::max(worst_est[k], hs.est[q] / std::sqrt(hs.rr0));
-          worst_iters[k] = std::max(worst_iters[k], hs.iters[q]);
-          S.unknown_updates += (double)ctx->nunk * hs.iters[q];
+        // FP64 true residuals of this sweep's shifts, up to 64 at a time
+        for (int q0 = 0; q0 < Jc; q0 += TEM_MAX_SHIFTS) {
+          const int nq = std::min(TEM_MAX_SHIFTS, Jc - q0);
+          HIPCHK(ctx, hipMemcpyAsync(shd, sre.data() + q0, nq * sizeof(double), hipMemcpyHostToDevice, st));
+          HIPCHK(ctx, hipMemcpyAsync(shd + TEM_MAX_SHIFTS, sim.data() + q0, nq * sizeof(double),
+                                     hipMemcpyHostToDevice, st));
+          tem::launch_cstencil(ctx->g, ys[i] + (size_t)q0 * n3, n3, ctx->d_dinv, shd, shd + TEM_MAX_SHIFTS, nq,
+                               (const double2*)ctx->gc.p, (double2*)ctx->P.p, n3, (double*)ctx->cpart.p, st);
+          tem::launch_reduce_rows((const double*)ctx->cpart.p, nq, cpb, shd + 2 * TEM_MAX_SHIFTS, st);
+          HIPCHK(ctx, hipGetLastError());
+          HIPCHK(ctx, hipMemcpyAsync(true2.data(), shd + 2 * TEM_MAX_SHIFTS, nq * sizeof(double),
+                                     hipMemcpyDeviceToHost, st));
+          HIPCHK(ctx, hipStreamSynchronize(st));
+          for (int q = q0; q < q0 + nq; ++q) {
+            const int k = order[c0 + q] % T;
+            worst_true[k] = std::max(worst_true[k], std::sqrt(true2[q - q0] / hs.rr0));
+            worst_est[k] = std::max(worst_est[k], hs.est[q] / std::sqrt(hs.rr0));
+            worst_iters[k] = std::max(worst_iters[k], hs.iters[q]);
+            S.unknown_updates += (double)ctx->nunk * hs.iters[q];
+          }
         }
       }
     }
@@ -2143,15 +2150,15 @@ int tem_adjoint(tem_ctx* ctx, const double* w, double* grad, tem_stats* stats) {
       if (e != hipSuccess) break;
       tem::launch_scale(ctx->n3, ctx->d_dinv, (const double*)ctx->f.p, (double*)ctx->slots[0].gvec.p, st);
       const tem_solve_opts& of = o;  // an FP64 solve (o is FP64 here)
-      SolveState fst;
+      std::unique_ptr<SolveState> fst(new SolveState());
       double secs = 0.0;
-      const int r1 = multishift_solve<double2>(ctx, sre, sim, ctx->fwd_s0, of, 1, &Ys, &fst, secs);
+      const int r1 = multishift_solve<double2>(ctx, sre, sim, ctx->fwd_s0, of, 1, &Ys, fst.get(), secs);
       if (r1 == TEM_ENOCONV) S.converged = 0;
       else if (r1 != TEM_OK) {
         cleanup();
         return r1;
       }
-      for (int j = 0; j < J; ++j) S.unknown_updates += (double)ctx->nunk * fst.iters[j];
+      for (int j = 0; j < J; ++j) S.unknown_updates += (double)ctx->nunk * fst->iters[j];
     }
     if (use_rows) {
       // lambda_j = sum_r gamma_jr (K + s_j M)^-1 q_r: one multi-shift solve per

@@ -12,7 +12,7 @@
 namespace tem {
 
 constexpr double kMu0 = 4e-7 * 3.14159265358979323846;  // Sec. 2.1
-constexpr int kMaxShifts = 64;
+constexpr int kMaxShifts = 320;  // shifts of one multi-shift solve (the public API takes up to 64 poles)
 constexpr int kMaxBlock = 64;       // deferred-update block length (iterations)
 constexpr int kReduceSlots = 65536;  // per-kernel partial sums (upper bound on stencil blocks)
 // block-coefficient sets: with the block update overlapped with the next
