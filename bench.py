@@ -90,7 +90,7 @@ def cpu_baseline(wl, s, seconds, gpu_iterations):
 
 
 def host_cpus():
-    """CPUs this process may run on (the GPU machine's share of the host)."""
+    """CPUs this process may run on (its share of the host)."""
     try:
         return len(os.sched_getaffinity(0))
     except AttributeError:
