@@ -99,13 +99,6 @@ def m_norm(prob, v):
     return np.sqrt(np.einsum("n,nk->k", prob.M, np.abs(v) ** 2))
 
 
-def cancellation(prob, X, C, U):
-    """kappa_c(t_k) = sum_j |c_jk| ||x_j||_M / ||u(t_k)||_M, the amplification
-    of per-solve errors into channel k by the residue sum."""
-    xn = m_norm(prob, X)
-    return (np.abs(C).T @ xn) / m_norm(prob, U)
-
-
 def dense_exact(prob, t, src=0):
     """u(t) = exp(-t M^-1 K) b, b = M^-1 f (eq. (expm)) from the eigen-
     decomposition of the symmetric M^-1/2 K M^-1/2 (tiny grids only)."""

@@ -211,12 +211,5 @@ class Problem:
         self.Q = sp.csr_matrix(np.array(Q)[:, self.idx]) if Q else sp.csr_matrix((0, len(self.idx)))
         self.n = len(self.idx)
 
-    def to_storage(self, x):
-        """Scatter interior vectors (n x ...) into storage edge order."""
-        x = np.asarray(x)
-        out = np.zeros((self.grid.n_edges,) + x.shape[1:], dtype=x.dtype)
-        out[self.idx] = x
-        return out
-
     def mass_derivative(self):
         return self.grid.mass_derivative_full(self.sigma)[self.idx]
