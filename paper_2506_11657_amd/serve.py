@@ -43,7 +43,7 @@ def footprint_bytes(nx, ny, nz, J, n_src, kind, block=64, n_rx=1, concurrent=4):
     operator arrays; one solver workspace per concurrent multi-shift solve
     (residual ring of `block` vectors, 3x that with overlapped updates, the
     seed's p and q in two slots each, right-hand side, per-shift p_j, 4 MiB of
-    partial sums); the solutions y_j of every concurrent source (of every source for the
+    partial sums and 2 MiB of solver state); the solutions y_j of every concurrent source (of every source for the
     adjoint, which keeps them); the residual and contraction scratch; for the
     adjoint, its right-hand sides per concurrent receiver row and its COCG
     vectors."""
@@ -55,7 +55,7 @@ def footprint_bytes(nx, ny, nz, J, n_src, kind, block=64, n_rx=1, concurrent=4):
     if kind == "adjoint":
         slots = max(slots, min(n_rx, concurrent))
     ring = 3 * block if os.environ.get("TEM_OVERLAP") == "1" else block   # 3 blocks with overlapped updates
-    slot = 8 * n3 * (ring + 6) + vec + (4 << 20)
+    slot = 8 * n3 * (ring + 6) + vec + (6 << 20)
     keep = vec * (n_src if kind == "adjoint" else conc)
     scratch = vec + 24 * n3
     adj = 0
