@@ -214,8 +214,8 @@ int tem_forward(tem_ctx *ctx, const tem_loop *src, int n_src,
  * (J*T + 1) complex vectors per concurrent source (up to 4).  stats: n_shifts
  * = J*T; iterations = seed iterations of the last source summed over its
  * sweeps; iters_per_shift[k], est_res[k] and true_res[k] hold, per channel k,
- * the maxima over that channel's J systems of every source.  No adjoint or Jacobian follows
- * this call (they return TEM_ESTATE). */
+ * the maxima over that channel's J systems of every source.  No adjoint or
+ * Jacobian follows this call (they return TEM_ESTATE). */
 int tem_forward_single(tem_ctx *ctx, const tem_loop *src, int n_src,
                        const tem_receiver *rx, int n_rx, int T, const double *t,
                        int J, const double *xi, const double *a, double alpha0,
