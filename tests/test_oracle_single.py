@@ -3,7 +3,8 @@ the first column of Table 1 (degree m for the target accuracy), Halphen's
 asymptotic error 2 H^(-m-1/2) (Sec. 3.3), the equioscillation that
 characterizes the best approximation (with de la Vallee Poussin's lower
 bound), the M-norm error bound against brute-force dense exp(-t M^-1 K) b,
-exact eigenvector behaviour and the solve counts of Sec. 3.1 and 5.1."""
+exact eigenvector behaviour, agreement with the shared-pole family within the
+two approximation errors, and the solve counts of Sec. 3.1 and 5.1."""
 import json
 import os
 
@@ -126,3 +127,18 @@ def test_eigenvector_gives_scalar_rational_function():
         floor = abs(f["alpha0"]) + np.array([np.sum(2 * np.abs(f["alpha"]) / np.abs(tl - f["xi"])) for tl in t * lam])
         err = np.abs(U - np.outer(b, rl)).max(axis=0) / np.abs(b).max()
         assert np.all(err <= 1e-12 * floor)
+
+
+def test_single_time_and_shared_family_agree_within_their_errors(tiny):
+    """Both rational forms approximate the same exp(-t M^-1 K) b: their
+    channels differ in the M-norm by at most (err_single + err_shared,k)
+    ||b||_M (triangle inequality with the Sec. 3.3 bound of each)."""
+    wl, P = tiny
+    fs = fit(10)
+    shared = rkfit.rkfit(wl.t, 24)
+    s, C = rkfit.shifts_and_coefficients(shared)
+    Us, _ = single.forward_single(P, fs, wl.t)
+    Uf = D.contract(D.solve_shifted(P, s, P.F[:, 0]), C)
+    bn = D.m_norm(P, P.F[:, 0] / P.M)
+    diff = D.m_norm(P, Us - Uf)
+    assert np.all(diff <= 1.01 * (fs["err"] + shared["err"]) * bn + 1e-12 * bn)
