@@ -8,7 +8,8 @@ the M-norms of the terms of eq. (rba) (the oracle's ``terms``) and eta = 1e-9.
 That is ten times below the contract's per-solve bar of 1e-8 (which bounds
 the channel error by 1e-8 S_k) and 33x above the oracle's own floor on these
 grids: its sparse-LU and banded-LU evaluations agree to 3.0e-11 S_k (m = 14,
-10^3, 10 channels) and 3.0e-11 S_k (m = 13, 8^3, 64 channels).  Every channel
+10^3, 10 channels) and 3.0e-11 S_k (m = 13, 8^3, 64 channels), held below
+1e-10 S_k on the CPU by test_single_time_parity_floor_two_direct_solvers.  Every channel
 here is dominated by cancellation in the residue sum (S_k / ||u_k||_M from 20
 to 3e11: the best-approximation residues are large), so no channel is held to
 a relative bar alone.

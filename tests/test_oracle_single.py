@@ -142,3 +142,32 @@ def test_single_time_and_shared_family_agree_within_their_errors(tiny):
     bn = D.m_norm(P, P.F[:, 0] / P.M)
     diff = D.m_norm(P, Us - Uf)
     assert np.all(diff <= 1.01 * (fs["err"] + shared["err"]) * bn + 1e-12 * bn)
+
+
+def _banded_rba(P, fit, t, src=0):
+    """eq. (rba) by a second direct solver: the banded LU of K + s M with
+    s = -xi/t_k and right-hand side f/t_k (the same systems divided by t_k)."""
+    B = D.BandedSolver(P.K)
+    f = P.F[:, src]
+    U = np.zeros((len(f), len(t)))
+    for k, tk in enumerate(t):
+        u = fit["alpha0"] * (f / P.M)
+        for p, a, pair in zip(fit["xi"], fit["alpha"], fit["pairs"]):
+            term = a * B.solve(P.M, -p / tk, f / tk)
+            u = u + (2 * term.real if pair else term.real)
+        U[:, k] = u
+    return U
+
+
+@pytest.mark.parametrize("n,m,T,seed", [(10, 14, 10, 5), (8, 13, 64, 6)])
+def test_single_time_parity_floor_two_direct_solvers(n, m, T, seed):
+    """The oracle's own floor on the grids of the GPU single-time parity
+    tests: its sparse-LU evaluation of t_k K - xi_i M and a banded LU of
+    K - (xi_i/t_k) M agree to 1e-10 S_k per channel (3.0e-11 measured), so the
+    GPU bar of 1e-9 S_k sits at least ten times above what the oracle fixes."""
+    wl = W.small_case(n, seed=seed, t=W.log_channels(1e-5, 1e-2, T))
+    P = yee.Problem(wl)
+    f = fit(m)
+    U, _, S = single.forward_single(P, f, wl.t, terms=True)
+    U2 = _banded_rba(P, f, wl.t)
+    assert np.all(D.m_norm(P, U - U2) <= 1e-10 * S)
