@@ -4,7 +4,8 @@ asymptotic error 2 H^(-m-1/2) (Sec. 3.3), the equioscillation that
 characterizes the best approximation (with de la Vallee Poussin's lower
 bound), the M-norm error bound against brute-force dense exp(-t M^-1 K) b,
 exact eigenvector behaviour, agreement with the shared-pole family within the
-two approximation errors, and the solve counts of Sec. 3.1 and 5.1."""
+two approximation errors, the solve counts of Sec. 3.1 and 5.1, and the
+oracle's own two-solver floor on the grids of the GPU parity tests."""
 import json
 import os
 
